@@ -1,0 +1,261 @@
+"""Benchmark of the FX-correlator hot path on one MI355X.
+
+One step = one pass of the whole hot path over one integration of synthetic
+voltages already resident in HBM: F-engine (channelising FFT + requantise),
+X-engine (Eq. 2 over the triangle of all input pairs, autos included), and a
+dump of the visibilities to a device buffer with reset.
+
+Default workload: 128 stations x 2 pols (256 inputs), 1024 channels, 1000
+spectra per integration, FP32 (complex64 Gaussian voltages plus three
+point-source tones).  The value is algorithmic complex multiply-accumulates
+(N(N+1)/2 * C * A per step) per second of the whole step.
+
+Also reported on one JSON line:
+  roofline     -- the dominant kernel (the X-engine), timed with HIP events on
+                  the correlator's stream, against the MFMA peak of its type;
+  forms        -- the same step in the FP16, int8 and FP8 forms, with X-engine
+                  speed-ups over FP32;
+  cpu_baseline -- the oracle (float64 direct DFT + triple-loop correlation)
+                  timed on a bounded channel sample on the host cores, which
+                  also gives each form's error against float64.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "X-engine TCMAC/s & % MFMA peak; int8/fp16 vs fp32 speed-up at stated error"
+# MI355X dense peaks (TFLOP/s or TOP/s); one CMAC = 8 real operations.
+PEAK = {"fp32": 157.3, "fp16": 2500.0, "fp8": 5000.0, "int8": 5000.0}
+DTYPE = {"fp32": "f32", "fp16": "f16", "fp8": "e4m3", "int8": "i8"}
+HBM_PEAK_GBS = 8000.0
+ELEM_BYTES = {"fp32": 4, "fp16": 2, "fp8": 1, "int8": 1}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mwa-128x2-c1024")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--forms", default="fp16,int8,fp8",
+                    help="other precisions to time on the same workload ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-channels", type=int, default=32)
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "xengine_traffic.json"),
+                    help="HBM bytes per X-engine launch measured with rocprofv3 counters")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events recorded on the correlator's stream (torch's current stream)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = []
+
+    def start(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record(self.torch.cuda.current_stream())
+        return e
+
+    def stop(self, s):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record(self.torch.cuda.current_stream())
+        self.pairs.append((s, e))
+
+    def mean_ms(self):
+        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs])) if self.pairs else float("nan")
+
+
+def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
+    """Time steps of F + X + dump; X timed on its own with events."""
+    inv = torch.from_numpy(synth.inv_scale(w, prec)).to("cuda") if prec != "fp32" else None
+    c = corr.Correlator(w.n_stations, w.n_pols, w.n_channels, w.n_integrate, prec)
+    out = c.new_visibilities()
+    A = w.n_integrate
+    ftimer, xtimer = Timer(torch), Timer(torch)
+
+    def step(timed):
+        if timed:
+            s = ftimer.start()
+        c.fengine(volts, A, inv)
+        if timed:
+            ftimer.stop(s)
+            s = xtimer.start()
+        c.xengine(A)
+        if timed:
+            xtimer.stop(s)
+        c.dump(out, reset=True)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return c, out, inv, wall, ftimer.mean_ms(), xtimer.mean_ms()
+
+
+def cpu_baseline(torch, oracle, synth, w, volts, results, n_chan):
+    """The oracle on a channel sample of the same integration; errors per form."""
+    C, N, A = w.n_channels, w.n_inputs, w.n_integrate
+    rng = np.random.default_rng(12345)
+    base = {0, C // 2, C - 1, *[b for b in w.tone_bins if b < C]}
+    others = [int(x) for x in rng.permutation(C) if int(x) not in base]
+    chans = sorted(base | set(others[: max(0, n_chan - len(base))]))
+    log(f"cpu_baseline: copying voltages to the host, oracle on {len(chans)} channels")
+    v = volts.cpu().numpy()
+    t0 = time.perf_counter()
+    S = oracle.fengine(v, C, A, chans)
+    V64 = oracle.xengine_f64(S)
+    t = time.perf_counter() - t0
+    B = N * (N + 1) // 2
+    cmacs = B * len(chans) * A
+    errors = {}
+    il, jl = np.tril_indices(N)
+    d = np.real(V64[:, [i * (i + 1) // 2 + i for i in range(N)]])
+    norm = np.sqrt(np.maximum(d[:, il] * d[:, jl], 1e-300))
+    for prec, (vis, s2) in results.items():
+        g = vis[chans].astype(np.float64)
+        g = g[..., 0] + 1j * g[..., 1]
+        if s2 is not None:
+            g = g * s2[chans][:, None]
+        eF = np.linalg.norm(g - V64, axis=1) / np.linalg.norm(V64, axis=1)
+        en = np.abs(g - V64) / norm
+        errors[prec] = {"max_rel_frobenius": float(eF.max()), "max_normalised": float(en.max())}
+    return {
+        "value": cmacs / t / 1e12,
+        "unit": "TCMAC/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": (f"float64 direct DFT (Eq. 1) + triple-loop correlation (Eq. 2) of {len(chans)} of "
+                   f"{C} channels, all {N} inputs x {A} spectra of the same integration; "
+                   f"{cmacs:.3e} CMAC in {t:.2f} s"),
+        "seconds": t,
+    }, errors
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(the multi-GPU frequency split is a design only)"}))
+        print("bench.py: only --gpus 1 is supported", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1305_5639_amd as corr
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    N, C, A = w.n_inputs, w.n_channels, w.n_integrate
+    B = N * (N + 1) // 2
+    cmacs = B * C * A
+    log(f"workload {w.name}: {N} inputs, {C} channels, {A} spectra, {cmacs:.3e} CMAC per step")
+    volts = synth.voltages(w, device="cuda")
+    torch.cuda.synchronize()
+
+    prec = args.precision
+    c, out, inv, wall, f_ms, x_ms = run_form(torch, corr, synth, w, prec, volts, args.steps, args.warmup)
+    s2_main = None
+    if prec == "int8":
+        s2_main = 1.0 / synth.inv_scale(w, prec).astype(np.float64) ** 2
+    results = {prec: (out.cpu().numpy(), s2_main)}
+    c.close()
+    log(f"{prec}: step {wall * 1e3:.3f} ms, F {f_ms:.3f} ms, X {x_ms:.3f} ms")
+
+    x_flops = 8.0 * cmacs
+    x_achieved = x_flops / (x_ms * 1e-3) / 1e12
+    traffic = None
+    try:
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        key = f"{w.name}/{prec}"
+        if key in tj:
+            traffic = tj[key]
+    except (OSError, ValueError):
+        pass
+    roofline = {"kernel": f"xengine_kernel<{prec}>", "bound": "mfma", "achieved": x_achieved,
+                "peak": PEAK[prec], "unit": "TFLOP/s", "frac": x_achieved / PEAK[prec],
+                "traffic": traffic}
+
+    forms = {}
+    for fp in [f for f in args.forms.split(",") if f and f != prec]:
+        cf, of, invf, wall_f, f_ms_f, x_ms_f = run_form(torch, corr, synth, w, fp, volts, args.steps, args.warmup)
+        s2 = None
+        if fp == "int8":
+            s2 = 1.0 / synth.inv_scale(w, fp).astype(np.float64) ** 2
+        results[fp] = (of.cpu().numpy(), s2)
+        cf.close()
+        del of
+        xt = cmacs / (x_ms_f * 1e-3) / 1e12
+        forms[fp] = {"ms_per_step": wall_f * 1e3, "fengine_ms": f_ms_f, "xengine_ms": x_ms_f,
+                     "fengine_hbm_gbs": (N * A * C * (8 + 2 * ELEM_BYTES[fp])) / (f_ms_f * 1e-3) / 1e9,
+                     "xengine_tcmacs": xt, "xengine_mfma_frac": 8 * xt / PEAK[fp],
+                     "xengine_speedup_vs_fp32": x_ms / x_ms_f if prec == "fp32" else None,
+                     "step_tcmacs": cmacs / wall_f / 1e12}
+        log(f"{fp}: step {wall_f * 1e3:.3f} ms, F {f_ms_f:.3f} ms, X {x_ms_f:.3f} ms")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cpu, errors = cpu_baseline(torch, oracle, synth, w, volts, results, args.cpu_channels)
+        for fp, e in errors.items():
+            if fp != prec:
+                forms[fp]["error_vs_float64"] = e
+        if prec in errors:
+            cpu["error_vs_float64_" + prec] = errors[prec]
+
+    line = {
+        "metric": METRIC,
+        "value": cmacs / wall / 1e12,
+        "unit": "TCMAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[prec],
+        "data": "synthetic (seeded complex Gaussian voltages plus point-source tones, resident in HBM)",
+        "config": {"workload": w.name, "n_stations": w.n_stations, "n_pols": w.n_pols,
+                   "n_inputs": N, "n_channels": C, "n_integrate": A, "precision": prec,
+                   "products": B, "cmac_per_step": cmacs,
+                   "step": "F-engine + X-engine + dump to device (reset)"},
+        "xengine_ms": x_ms,
+        "fengine_ms": f_ms,
+        "xengine_tcmacs": cmacs / (x_ms * 1e-3) / 1e12,
+        "fengine_hbm_gbs": (N * A * C * (8 + 2 * ELEM_BYTES[prec])) / (f_ms * 1e-3) / 1e9,
+        "roofline": roofline,
+        "forms": forms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

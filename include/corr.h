@@ -1,0 +1,205 @@
+/*
+ * corr.h -- C ABI of the MI355X FX-correlator hot path.
+ *
+ * The library implements, on one gfx950 GPU, the two engines of an FX
+ * correlator (Wang & Harris, "Scaling Radio Astronomy Signal Correlation on
+ * Heterogeneous Supercomputers Using Various Data Distribution
+ * Methodologies", Exp. Astron. 2013):
+ *
+ *   F-engine (Section 2, Eq. 1): every input stream is cut into consecutive,
+ *     non-overlapping blocks of C samples and each block is transformed with a
+ *     forward, unnormalised C-point complex DFT, S[k] = sum_n s[n] e^{-j 2 pi k n / C},
+ *     giving C channels in natural order.  No window, filter bank or fringe
+ *     rotation (the paper's F-engine carries none, Section 5).
+ *
+ *   X-engine (Section 2, Eq. 2): for every channel k and every pair (i, j) of
+ *     the triangle of non-redundant input pairs, autos included (Section 4),
+ *     C_ij[k] = sum_a conj(S_{a,i}[k]) S_{a,j}[k] -- conjugate on the FIRST
+ *     index -- summed (not averaged) over the spectra a of the integration.
+ *
+ * An "input" is one station-polarisation stream: input p = station*n_pols + pol
+ * (a stream carries one polarisation of one antenna, Section 3).  N inputs give
+ * N(N+1)/2 products per channel.
+ *
+ * Conventions for every function:
+ *   - Every function returns a corr_status; nothing throws across the ABI.
+ *   - Output parameters are written only on CORR_OK.
+ *   - Argument validation runs on the CPU before any HIP call, so invalid
+ *     arguments never touch the device.
+ *   - All device work is enqueued on the HIP stream given to corr_create and
+ *     is asynchronous, except where a function says it synchronises.  Caller
+ *     buffers must stay valid until that work completes.
+ *   - Pointers named d_* are device pointers; the caller owns them.  The
+ *     library owns the handle, its spectra buffer and its accumulators.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef CORR_H
+#define CORR_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define CORR_API __attribute__((visibility("default")))
+#else
+#define CORR_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct corr_ctx *corr_handle;
+
+typedef enum {
+    CORR_OK = 0,
+    CORR_E_INVALID_ARG = 1, /* a null pointer, out-of-range value or misaligned buffer   */
+    CORR_E_UNSUPPORTED = 2, /* a well-formed request outside what the library implements */
+    CORR_E_NOMEM = 3,       /* the plan does not fit the device memory budget            */
+    CORR_E_OVERFLOW = 4,    /* the int8 integration could overflow its int32 accumulators */
+    CORR_E_STATE = 5,       /* calls made out of order (e.g. X before any F)             */
+    CORR_E_HIP = 6          /* a HIP runtime error; corr_last_error() holds its text     */
+} corr_status;
+
+/* Arithmetic forms of the X-engine input (the F-engine requantises into it).
+ *   CORR_FP32     : float32 spectra, float32 accumulation.
+ *   CORR_FP16     : IEEE binary16 spectra (round half to even, saturating at
+ *                   +-65504), float32 accumulation.
+ *   CORR_FP8_E4M3 : OCP FP8 E4M3 spectra (round half to even, saturating at
+ *                   +-448, no infinities), float32 accumulation.
+ *   CORR_INT8     : int8 spectra, round half to even, clamped to [-127, 127]
+ *                   (the paper's inputs are 8-bit integers, Section 5), exact
+ *                   int32 accumulation. */
+typedef enum { CORR_FP32 = 0, CORR_FP16 = 1, CORR_FP8_E4M3 = 2, CORR_INT8 = 3 } corr_precision;
+
+/* Layout of one channel's products in a dump.
+ *   CORR_TRI_LOWER : rows i in [0,N), columns j <= i, b = i(i+1)/2 + j, value C_ij.
+ *   CORR_TRI_UPPER : rows i, columns j >= i, b = i*N - i(i-1)/2 + (j - i), value C_ij.
+ *   CORR_FULL      : all N*N products, b = i*N + j (C_ij = conj(C_ji)). */
+typedef enum { CORR_TRI_LOWER = 0, CORR_TRI_UPPER = 1, CORR_FULL = 2 } corr_layout;
+
+/* Order of a dump: channel-major [k][b] or baseline-major [b][k]. */
+typedef enum { CORR_CHAN_MAJOR = 0, CORR_BASELINE_MAJOR = 1 } corr_order;
+
+typedef struct {
+    int32_t n_stations;      /* >= 1                                                     */
+    int32_t n_pols;          /* 1 or 2; input p = station*n_pols + pol                    */
+    int32_t n_channels;      /* C = FFT length = channel count; power of two, 16..8192   */
+    int32_t n_integrate;     /* spectra held per F-engine call (capacity of the spectra
+                                buffer); also the largest n_spectra of one call          */
+    int32_t precision;       /* corr_precision                                           */
+    int32_t layout;          /* corr_layout used by corr_dump_visibilities               */
+    int32_t order;           /* corr_order used by corr_dump_visibilities                */
+    int32_t reserved;        /* must be 0                                                */
+    uint64_t device_mem_cap; /* bytes the plan may use; 0 = the device's free memory     */
+} corr_params;
+
+/* Limits. */
+#define CORR_MIN_CHANNELS 16
+#define CORR_MAX_CHANNELS 8192
+#define CORR_MAX_INPUTS 8192
+/* Largest int8 integration whose worst case, 2*127^2 per spectrum, fits int32. */
+#define CORR_INT8_MAX_INTEGRATE 66572
+
+/* Number of products N(N+1)/2 per channel, N = n_stations*n_pols; -1 on bad params. */
+CORR_API int64_t corr_n_products(const corr_params *params);
+
+/* Bytes one corr_dump_visibilities writes: products in the chosen layout x
+ * channels x 8 (complex64 for float forms, an (re, im) int32 pair for int8);
+ * -1 on bad params. */
+CORR_API int64_t corr_visibility_bytes(const corr_params *params);
+
+/* Bytes of n_spectra spectra in the public spectra layout (see corr_xengine);
+ * -1 on bad params. */
+CORR_API int64_t corr_spectra_bytes(const corr_params *params, int32_t n_spectra);
+
+/*
+ * Plan and allocate a correlator for the given shape.  Validates params
+ * (CORR_E_INVALID_ARG / CORR_E_UNSUPPORTED), sizes the spectra buffer
+ * (n_integrate spectra), the accumulators (C * N(N+1)/2 complex) and the
+ * twiddle table, and fails with CORR_E_NOMEM when they exceed device_mem_cap
+ * (or the device's free memory when the cap is 0): the failure mode of a GPU
+ * that cannot hold all baselines of one FFT length (Section 3).  For
+ * CORR_INT8, n_integrate above CORR_INT8_MAX_INTEGRATE is CORR_E_OVERFLOW.
+ * hip_stream is a hipStream_t (NULL = the null stream); all later work of the
+ * handle is enqueued on it.  Accumulators start at zero.  Launches no kernel.
+ */
+CORR_API corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle *out);
+
+/* Release the handle and its device memory (synchronises its stream).
+ * A NULL handle is CORR_E_INVALID_ARG. */
+CORR_API corr_status corr_destroy(corr_handle h);
+
+/*
+ * F-engine (Eq. 1) with the requantise epilogue of the handle's precision.
+ *   d_volts     : complex64 (float re, im) voltages, [n_inputs][ld_samples];
+ *                 spectrum a of input p is the DFT of samples
+ *                 [a*C, (a+1)*C) of row p.  8-byte aligned.
+ *   ld_samples  : row stride in complex samples, >= n_spectra*C.
+ *   n_spectra   : 1 .. n_integrate spectra to channelise.
+ *   d_inv_scale : float32 [C] per-channel scale inv_s[k]; each spectrum value
+ *                 is multiplied by inv_s[k] before requantisation, and the
+ *                 X-engine multiplies the integrated products by s_k^2 =
+ *                 1/inv_s[k]^2 so that dumps are in voltage units (the int8
+ *                 form dumps raw integer sums instead).  Required for
+ *                 CORR_INT8; NULL means 1.0 for the other forms.
+ * The spectra replace the handle's previous spectra.
+ */
+CORR_API corr_status corr_fengine(corr_handle h, const void *d_volts, int64_t ld_samples,
+                         int32_t n_spectra, const float *d_inv_scale);
+
+/*
+ * X-engine (Eq. 2): add n_spectra spectra into the accumulators.
+ *   d_spectra   : NULL = the first n_spectra spectra of the last corr_fengine
+ *                 (n_spectra above that call's count is CORR_E_STATE); else
+ *                 caller spectra in the public layout
+ *                 [n_spectra][n_channels][n_inputs][2] of the precision's
+ *                 element (float32, binary16, E4M3 byte or int8; re then im),
+ *                 16-byte aligned, n_spectra <= n_integrate.  Caller spectra
+ *                 overwrite the handle's spectra buffer.
+ *   d_inv_scale : with caller spectra of the FP16 / FP8 forms, the float32
+ *                 per-channel inv_s[k] they were scaled with (NULL = 1.0);
+ *                 must be NULL when d_spectra is NULL (the F-engine's scale
+ *                 applies) and for CORR_FP32 / CORR_INT8.
+ * For CORR_INT8, a running integration longer than CORR_INT8_MAX_INTEGRATE
+ * spectra since the last reset is CORR_E_OVERFLOW (nothing is launched).
+ */
+CORR_API corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra,
+                         const float *d_inv_scale);
+
+/*
+ * Write the integrated visibilities to dst in the handle's layout and order:
+ * complex64 per product for the float forms (scaled to voltage units),
+ * (re, im) int32 per product for CORR_INT8 (raw integer sums, exact).
+ * dst holds corr_visibility_bytes(params) bytes; dst_on_device = 1 for a
+ * device pointer (asynchronous), 0 for host memory (synchronises the stream).
+ * reset = 1 zeroes the accumulators afterwards (a new integration starts);
+ * reset = 0 keeps them, so further corr_xengine calls continue the same
+ * integration (resume).
+ */
+CORR_API corr_status corr_dump_visibilities(corr_handle h, void *dst, int32_t dst_on_device, int32_t reset);
+
+/*
+ * Copy the spectra held by the handle (the last F-engine output, i.e. the
+ * requantised values the X-engine consumes) to dst in the public spectra
+ * layout [n_spectra][n_channels][n_inputs][2] of the precision's element.
+ * dst holds corr_spectra_bytes(params, n) bytes, n = spectra held.  With
+ * dst_on_device = 0 the call synchronises the stream.  For checking and
+ * debugging; not on the hot path.
+ */
+CORR_API corr_status corr_copy_spectra(corr_handle h, void *dst, int32_t dst_on_device);
+
+/* Number of spectra currently held, and spectra integrated since the last reset. */
+CORR_API corr_status corr_get_counts(corr_handle h, int32_t *n_held, int64_t *n_integrated);
+
+/* Static text of a status code. */
+CORR_API const char *corr_status_string(corr_status s);
+
+/* Text of the last error recorded on the handle (HIP error strings included);
+ * "" if none.  Valid until the next call on the handle. */
+CORR_API const char *corr_last_error(corr_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORR_H */

@@ -81,14 +81,17 @@ void oracle_fengine(const float *volts, int64_t ld, int n_inputs, int C,
         const int p = (int)(ap % n_inputs);
         const float *s = volts + 2 * ((int64_t)p * ld + (int64_t)a * C);
         for (int c = 0; c < n_chans; ++c) {
-            const int64_t k = chans[c];
+            const int k = chans[c];
             double re = 0.0, im = 0.0;
+            int m = 0; /* m = (k n) mod C, advanced by k each step */
             for (int n = 0; n < C; ++n) {
-                const int64_t m = (k * n) % C;
                 const double sr = (double)s[2 * n], si = (double)s[2 * n + 1];
                 const double wr = w[2 * m], wi = w[2 * m + 1];
                 re += sr * wr - si * wi;
                 im += sr * wi + si * wr;
+                m += k;
+                if (m >= C)
+                    m -= C;
             }
             double *o = S + 2 * ((ap) * n_chans + c);
             o[0] = re;

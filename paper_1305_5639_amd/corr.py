@@ -1,0 +1,273 @@
+"""ctypes binding of libcorr.so, the MI355X FX-correlator library.
+
+The functions carry the C ABI's names and only marshal arguments: torch
+tensors become device pointers, the HIP stream defaults to torch's current
+stream, and a non-OK status raises CorrError.  Every step of the correlator
+runs in the library's HIP kernels; there is no Python or CPU fallback, and
+loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  -- loads the process's HIP runtime before libcorr.so
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcorr.so")
+
+CORR_OK = 0
+CORR_E_INVALID_ARG = 1
+CORR_E_UNSUPPORTED = 2
+CORR_E_NOMEM = 3
+CORR_E_OVERFLOW = 4
+CORR_E_STATE = 5
+CORR_E_HIP = 6
+
+CORR_FP32, CORR_FP16, CORR_FP8_E4M3, CORR_INT8 = 0, 1, 2, 3
+CORR_TRI_LOWER, CORR_TRI_UPPER, CORR_FULL = 0, 1, 2
+CORR_CHAN_MAJOR, CORR_BASELINE_MAJOR = 0, 1
+CORR_MIN_CHANNELS, CORR_MAX_CHANNELS, CORR_MAX_INPUTS = 16, 8192, 8192
+CORR_INT8_MAX_INTEGRATE = 66572
+
+PRECISIONS = {"fp32": CORR_FP32, "fp16": CORR_FP16, "fp8": CORR_FP8_E4M3, "int8": CORR_INT8}
+LAYOUTS = {"lower": CORR_TRI_LOWER, "upper": CORR_TRI_UPPER, "full": CORR_FULL}
+ORDERS = {"chan": CORR_CHAN_MAJOR, "baseline": CORR_BASELINE_MAJOR}
+# element type of spectra per precision (re, im pairs)
+SPECTRA_DTYPE = {CORR_FP32: torch.float32, CORR_FP16: torch.float16,
+                 CORR_FP8_E4M3: torch.float8_e4m3fn, CORR_INT8: torch.int8}
+
+# Header names of every exported function (checked by the ABI tests).
+ABI_FUNCTIONS = (
+    "corr_n_products", "corr_visibility_bytes", "corr_spectra_bytes", "corr_create",
+    "corr_destroy", "corr_fengine", "corr_xengine", "corr_dump_visibilities",
+    "corr_copy_spectra", "corr_get_counts", "corr_status_string", "corr_last_error",
+)
+
+
+class corr_params(ctypes.Structure):
+    _fields_ = [
+        ("n_stations", ctypes.c_int32),
+        ("n_pols", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("n_integrate", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("device_mem_cap", ctypes.c_uint64),
+    ]
+
+
+class CorrError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {corr_status_string(status)} ({detail})")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with paper_1305_5639_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        PP = ctypes.POINTER(corr_params)
+        L.corr_n_products.argtypes = [PP]
+        L.corr_n_products.restype = i64
+        L.corr_visibility_bytes.argtypes = [PP]
+        L.corr_visibility_bytes.restype = i64
+        L.corr_spectra_bytes.argtypes = [PP, i32]
+        L.corr_spectra_bytes.restype = i64
+        L.corr_create.argtypes = [PP, P, ctypes.POINTER(P)]
+        L.corr_destroy.argtypes = [P]
+        L.corr_fengine.argtypes = [P, P, i64, i32, P]
+        L.corr_xengine.argtypes = [P, P, i32, P]
+        L.corr_dump_visibilities.argtypes = [P, P, i32, i32]
+        L.corr_copy_spectra.argtypes = [P, P, i32]
+        L.corr_get_counts.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.corr_status_string.argtypes = [i32]
+        L.corr_status_string.restype = ctypes.c_char_p
+        L.corr_last_error.argtypes = [P]
+        L.corr_last_error.restype = ctypes.c_char_p
+        for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_xengine",
+                  "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts"):
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------------------
+# marshalling helpers
+# --------------------------------------------------------------------------
+def make_params(n_stations, n_pols, n_channels, n_integrate, precision="fp32", layout="lower",
+                order="chan", device_mem_cap=0) -> corr_params:
+    prec = PRECISIONS.get(precision, precision)
+    lay = LAYOUTS.get(layout, layout)
+    odr = ORDERS.get(order, order)
+    return corr_params(int(n_stations), int(n_pols), int(n_channels), int(n_integrate), int(prec),
+                       int(lay), int(odr), 0, int(device_mem_cap))
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, torch.Tensor):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    import numpy as np
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    raise TypeError(f"cannot pass {type(x)} as a pointer")
+
+
+def _on_device(x) -> int:
+    return 1 if isinstance(x, torch.Tensor) and x.is_cuda else 0
+
+
+def _check(status: int, where: str, h=None):
+    if status != CORR_OK:
+        raise CorrError(status, where, corr_last_error(h))
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return stream
+
+
+# --------------------------------------------------------------------------
+# the ABI, by name
+# --------------------------------------------------------------------------
+def corr_status_string(status: int) -> str:
+    return lib().corr_status_string(int(status)).decode()
+
+
+def corr_last_error(h=None) -> str:
+    return lib().corr_last_error(h).decode()
+
+
+def corr_n_products(params: corr_params) -> int:
+    return int(lib().corr_n_products(ctypes.byref(params)))
+
+
+def corr_visibility_bytes(params: corr_params) -> int:
+    return int(lib().corr_visibility_bytes(ctypes.byref(params)))
+
+
+def corr_spectra_bytes(params: corr_params, n_spectra: int) -> int:
+    return int(lib().corr_spectra_bytes(ctypes.byref(params), int(n_spectra)))
+
+
+def corr_create(params: corr_params, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().corr_create(ctypes.byref(params), _stream(stream), ctypes.byref(h)), "corr_create")
+    return h
+
+
+def corr_destroy(h) -> None:
+    _check(lib().corr_destroy(h), "corr_destroy", h)
+
+
+def corr_fengine(h, volts, n_spectra: int, inv_scale=None, ld_samples: int | None = None) -> None:
+    if ld_samples is None:
+        ld_samples = volts.shape[-1]
+    _check(lib().corr_fengine(h, _ptr(volts), int(ld_samples), int(n_spectra), _ptr(inv_scale)),
+           "corr_fengine", h)
+
+
+def corr_xengine(h, spectra, n_spectra: int, inv_scale=None) -> None:
+    _check(lib().corr_xengine(h, _ptr(spectra), int(n_spectra), _ptr(inv_scale)), "corr_xengine", h)
+
+
+def corr_dump_visibilities(h, dst, reset: bool = True, dst_on_device: int | None = None) -> None:
+    dev = _on_device(dst) if dst_on_device is None else int(dst_on_device)
+    _check(lib().corr_dump_visibilities(h, _ptr(dst), dev, int(bool(reset))), "corr_dump_visibilities", h)
+
+
+def corr_copy_spectra(h, dst, dst_on_device: int | None = None) -> None:
+    dev = _on_device(dst) if dst_on_device is None else int(dst_on_device)
+    _check(lib().corr_copy_spectra(h, _ptr(dst), dev), "corr_copy_spectra", h)
+
+
+def corr_get_counts(h) -> tuple[int, int]:
+    a, b = ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().corr_get_counts(h, ctypes.byref(a), ctypes.byref(b)), "corr_get_counts", h)
+    return a.value, b.value
+
+
+# --------------------------------------------------------------------------
+# a small owning wrapper
+# --------------------------------------------------------------------------
+class Correlator:
+    """Owns one handle; methods map one-to-one onto the ABI calls."""
+
+    def __init__(self, n_stations, n_pols, n_channels, n_integrate, precision="fp32", layout="lower",
+                 order="chan", device_mem_cap=0, stream=None):
+        self.params = make_params(n_stations, n_pols, n_channels, n_integrate, precision, layout, order,
+                                  device_mem_cap)
+        self.n_inputs = n_stations * n_pols
+        self.n_channels = n_channels
+        self.precision = self.params.precision
+        self.handle = corr_create(self.params, stream)
+
+    def fengine(self, volts, n_spectra, inv_scale=None, ld_samples=None):
+        corr_fengine(self.handle, volts, n_spectra, inv_scale, ld_samples)
+
+    def xengine(self, n_spectra, spectra=None, inv_scale=None):
+        corr_xengine(self.handle, spectra, n_spectra, inv_scale)
+
+    def visibility_shape(self):
+        """Shape of a dump as a tensor whose last axis is (re, im)."""
+        N, C = self.n_inputs, self.n_channels
+        B = N * N if self.params.layout == CORR_FULL else N * (N + 1) // 2
+        return (C, B, 2) if self.params.order == CORR_CHAN_MAJOR else (B, C, 2)
+
+    def new_visibilities(self, device="cuda"):
+        dt = torch.int32 if self.precision == CORR_INT8 else torch.float32
+        return torch.empty(self.visibility_shape(), dtype=dt, device=device)
+
+    def dump(self, dst=None, reset=True, device="cuda"):
+        if dst is None:
+            dst = self.new_visibilities(device)
+        corr_dump_visibilities(self.handle, dst, reset)
+        return dst
+
+    def spectra(self, device="cuda"):
+        n_held, _ = corr_get_counts(self.handle)
+        dst = torch.empty((n_held, self.n_channels, self.n_inputs, 2),
+                          dtype=SPECTRA_DTYPE[self.precision], device=device)
+        corr_copy_spectra(self.handle, dst)
+        return dst
+
+    def counts(self):
+        return corr_get_counts(self.handle)
+
+    def close(self):
+        if self.handle:
+            corr_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

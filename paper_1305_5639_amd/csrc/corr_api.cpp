@@ -1,0 +1,403 @@
+// C ABI of the correlator: argument validation, the plan (buffer sizes and
+// the device-memory budget), integration state, and the launches.
+//
+// Validation always runs before the first HIP call of a function, so every
+// invalid-argument, budget and overflow error is decided on the CPU.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "corr.h"
+#include "corr_internal.h"
+
+using namespace corr;
+
+struct corr_ctx {
+    corr_params p{};
+    int N = 0, C = 0, prec = 0, TB = 0, n_tb_cap = 0;
+    int64_t B = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void *spec = nullptr;
+    size_t spec_bytes = 0;
+    void *acc = nullptr;
+    size_t acc_bytes = 0;
+    float2 *twiddle = nullptr;
+    float *scale2 = nullptr;          // s_k^2 of the F-engine's spectra
+    float *scale2_user = nullptr;     // s_k^2 of caller spectra
+    void *dump_tmp = nullptr;         // staging for converted dumps to host
+    int n_held = 0;                   // spectra in the buffer
+    bool held_from_fengine = false;
+    int64_t n_integrated = 0;         // spectra integrated since the last reset
+    bool acc_zero = true;             // accumulators logically zero
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+corr_status fail(corr_ctx *h, corr_status s, const std::string &msg) {
+    if (h)
+        h->err = msg;
+    else
+        g_err = msg;
+    return s;
+}
+
+corr_status hip_fail(corr_ctx *h, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(h, e == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP, m);
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Validates params; fills N, B, C, prec on success.  No HIP calls.
+corr_status check_params(const corr_params *p, std::string &msg) {
+    if (!p) {
+        msg = "params is NULL";
+        return CORR_E_INVALID_ARG;
+    }
+    if (p->n_stations < 1) {
+        msg = "n_stations must be >= 1";
+        return CORR_E_INVALID_ARG;
+    }
+    if (p->n_pols != 1 && p->n_pols != 2) {
+        msg = "n_pols must be 1 or 2";
+        return CORR_E_INVALID_ARG;
+    }
+    if (!is_pow2(p->n_channels)) {
+        msg = "n_channels must be a power of two";
+        return CORR_E_INVALID_ARG;
+    }
+    if (p->n_channels < CORR_MIN_CHANNELS || p->n_channels > CORR_MAX_CHANNELS) {
+        msg = "n_channels outside 16..8192";
+        return CORR_E_UNSUPPORTED;
+    }
+    if (p->n_integrate < 1) {
+        msg = "n_integrate must be >= 1";
+        return CORR_E_INVALID_ARG;
+    }
+    if (p->precision < CORR_FP32 || p->precision > CORR_INT8) {
+        msg = "unknown precision";
+        return CORR_E_INVALID_ARG;
+    }
+    if (p->layout < CORR_TRI_LOWER || p->layout > CORR_FULL) {
+        msg = "unknown layout";
+        return CORR_E_INVALID_ARG;
+    }
+    if (p->order < CORR_CHAN_MAJOR || p->order > CORR_BASELINE_MAJOR) {
+        msg = "unknown order";
+        return CORR_E_INVALID_ARG;
+    }
+    if (p->reserved != 0) {
+        msg = "reserved must be 0";
+        return CORR_E_INVALID_ARG;
+    }
+    const int64_t N = (int64_t)p->n_stations * p->n_pols;
+    if (N > CORR_MAX_INPUTS) {
+        msg = "more than 8192 inputs";
+        return CORR_E_UNSUPPORTED;
+    }
+    if (p->precision == CORR_INT8 && p->n_integrate > CORR_INT8_MAX_INTEGRATE) {
+        msg = "int8 integration longer than 66572 spectra could overflow int32";
+        return CORR_E_OVERFLOW;
+    }
+    return CORR_OK;
+}
+
+int64_t n_inputs(const corr_params *p) { return (int64_t)p->n_stations * p->n_pols; }
+
+int64_t layout_products(const corr_params *p) {
+    const int64_t N = n_inputs(p);
+    return p->layout == CORR_FULL ? N * N : N * (N + 1) / 2;
+}
+
+bool default_dump(const corr_params *p) { return p->layout == CORR_TRI_LOWER && p->order == CORR_CHAN_MAJOR; }
+
+bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t corr_n_products(const corr_params *params) {
+    std::string m;
+    if (check_params(params, m) != CORR_OK) return -1;
+    const int64_t N = n_inputs(params);
+    return N * (N + 1) / 2;
+}
+
+int64_t corr_visibility_bytes(const corr_params *params) {
+    std::string m;
+    if (check_params(params, m) != CORR_OK) return -1;
+    return layout_products(params) * params->n_channels * 8;
+}
+
+int64_t corr_spectra_bytes(const corr_params *params, int32_t n_spectra) {
+    std::string m;
+    if (check_params(params, m) != CORR_OK || n_spectra < 0) return -1;
+    return (int64_t)n_spectra * params->n_channels * n_inputs(params) * 2 * elem_bytes(params->precision);
+}
+
+const char *corr_status_string(corr_status s) {
+    switch (s) {
+    case CORR_OK: return "CORR_OK";
+    case CORR_E_INVALID_ARG: return "CORR_E_INVALID_ARG: invalid argument";
+    case CORR_E_UNSUPPORTED: return "CORR_E_UNSUPPORTED: unsupported configuration";
+    case CORR_E_NOMEM: return "CORR_E_NOMEM: device memory budget exceeded";
+    case CORR_E_OVERFLOW: return "CORR_E_OVERFLOW: int8 integration could overflow int32";
+    case CORR_E_STATE: return "CORR_E_STATE: call out of order";
+    case CORR_E_HIP: return "CORR_E_HIP: HIP runtime error";
+    default: return "unknown corr_status";
+    }
+}
+
+const char *corr_last_error(corr_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle *out) {
+    std::string msg;
+    corr_status s = check_params(params, msg);
+    if (s != CORR_OK) return fail(nullptr, s, msg);
+    if (!out) return fail(nullptr, CORR_E_INVALID_ARG, "out is NULL");
+
+    const int N = (int)n_inputs(params);
+    const int C = params->n_channels;
+    const int prec = params->precision;
+    const int TB = time_block(prec);
+    const int n_tb_cap = (params->n_integrate + TB - 1) / TB;
+    const size_t spec_bytes = (size_t)C * n_tb_cap * N * 2 * kRowBytes;
+    const int64_t B = (int64_t)N * (N + 1) / 2;
+    const size_t acc_bytes = (size_t)C * B * 8;
+    const size_t small_bytes = (size_t)C * 8 + 2 * (size_t)C * 4;
+    const size_t dump_bytes = default_dump(params) ? 0 : (size_t)corr_visibility_bytes(params);
+    const size_t need = spec_bytes + acc_bytes + small_bytes + dump_bytes;
+    if (params->device_mem_cap && need > params->device_mem_cap) {
+        char b[160];
+        snprintf(b, sizeof b, "plan needs %zu bytes, cap is %llu", need,
+                 (unsigned long long)params->device_mem_cap);
+        return fail(nullptr, CORR_E_NOMEM, b);
+    }
+
+    // ---- HIP from here on ----
+    corr_ctx *h = new (std::nothrow) corr_ctx();
+    if (!h) return fail(nullptr, CORR_E_NOMEM, "host allocation failed");
+    h->p = *params;
+    h->N = N;
+    h->C = C;
+    h->prec = prec;
+    h->TB = TB;
+    h->n_tb_cap = n_tb_cap;
+    h->B = B;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->spec_bytes = spec_bytes;
+    h->acc_bytes = acc_bytes;
+
+    auto cleanup_fail = [&](corr_status st, const std::string &m) {
+        g_err = m;
+        corr_destroy(h);
+        return st;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        std::string m = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        delete h;
+        return fail(nullptr, CORR_E_HIP, m);
+    }
+    if (!params->device_mem_cap) {
+        size_t fr = 0, tot = 0;
+        e = hipMemGetInfo(&fr, &tot);
+        if (e != hipSuccess) {
+            std::string m = std::string("hipMemGetInfo: ") + hipGetErrorString(e);
+            delete h;
+            return fail(nullptr, CORR_E_HIP, m);
+        }
+        if (need > fr) {
+            char b[160];
+            snprintf(b, sizeof b, "plan needs %zu bytes, device has %zu free", need, fr);
+            delete h;
+            return fail(nullptr, CORR_E_NOMEM, b);
+        }
+    }
+    if ((e = hipMalloc(&h->spec, spec_bytes)) != hipSuccess)
+        return cleanup_fail(e == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP, "hipMalloc spectra failed");
+    if ((e = hipMalloc(&h->acc, acc_bytes)) != hipSuccess)
+        return cleanup_fail(e == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP, "hipMalloc accumulators failed");
+    if ((e = hipMalloc(&h->twiddle, (size_t)C * sizeof(float2))) != hipSuccess ||
+        (e = hipMalloc(&h->scale2, (size_t)C * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&h->scale2_user, (size_t)C * sizeof(float))) != hipSuccess)
+        return cleanup_fail(CORR_E_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+
+    // Twiddles W[m] = exp(-j 2 pi m / C), computed in float64, rounded to float32.
+    std::vector<float2> tw(C);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int m = 0; m < C; ++m) {
+        const double ang = two_pi * (double)m / (double)C;
+        tw[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+    }
+    if ((e = hipMemcpy(h->twiddle, tw.data(), (size_t)C * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup_fail(CORR_E_HIP, std::string("hipMemcpy twiddles: ") + hipGetErrorString(e));
+    *out = h;
+    return CORR_OK;
+}
+
+corr_status corr_destroy(corr_handle h) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (h->spec || h->acc) (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->spec);
+    (void)hipFree(h->acc);
+    (void)hipFree(h->twiddle);
+    (void)hipFree(h->scale2);
+    (void)hipFree(h->scale2_user);
+    (void)hipFree(h->dump_tmp);
+    delete h;
+    return CORR_OK;
+}
+
+corr_status corr_fengine(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
+                         const float *d_inv_scale) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (!d_volts) return fail(h, CORR_E_INVALID_ARG, "d_volts is NULL");
+    if (!aligned(d_volts, 8)) return fail(h, CORR_E_INVALID_ARG, "d_volts must be 8-byte aligned");
+    if (d_inv_scale && !aligned(d_inv_scale, 4)) return fail(h, CORR_E_INVALID_ARG, "d_inv_scale misaligned");
+    if (n_spectra < 1 || n_spectra > h->p.n_integrate)
+        return fail(h, CORR_E_INVALID_ARG, "n_spectra must be in 1..n_integrate");
+    if (ld_samples < (int64_t)n_spectra * h->C)
+        return fail(h, CORR_E_INVALID_ARG, "ld_samples < n_spectra * n_channels");
+    if (h->prec == P_INT8 && !d_inv_scale)
+        return fail(h, CORR_E_INVALID_ARG, "int8 needs a per-channel scale");
+
+    hipError_t e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
+    e = launch_fengine(h->prec, h->C, h->N, static_cast<const float2 *>(d_volts), ld_samples, n_spectra,
+                       d_inv_scale, h->twiddle, h->spec, h->n_tb_cap, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "fengine launch");
+    h->n_held = n_spectra;
+    h->held_from_fengine = true;
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra, const float *d_inv_scale) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (n_spectra < 1) return fail(h, CORR_E_INVALID_ARG, "n_spectra must be >= 1");
+    if (d_spectra) {
+        if (!aligned(d_spectra, 16)) return fail(h, CORR_E_INVALID_ARG, "d_spectra must be 16-byte aligned");
+        if (n_spectra > h->p.n_integrate) return fail(h, CORR_E_INVALID_ARG, "n_spectra > n_integrate");
+        if (d_inv_scale && (h->prec == P_FP32 || h->prec == P_INT8))
+            return fail(h, CORR_E_INVALID_ARG, "d_inv_scale applies only to FP16/FP8 caller spectra");
+        if (d_inv_scale && !aligned(d_inv_scale, 4)) return fail(h, CORR_E_INVALID_ARG, "d_inv_scale misaligned");
+    } else {
+        if (d_inv_scale) return fail(h, CORR_E_INVALID_ARG, "d_inv_scale must be NULL for held spectra");
+        if (h->n_held == 0) return fail(h, CORR_E_STATE, "no spectra held: call corr_fengine first");
+        if (n_spectra > h->n_held) return fail(h, CORR_E_STATE, "n_spectra exceeds the spectra held");
+    }
+    if (h->prec == P_INT8 && h->n_integrated + n_spectra > CORR_INT8_MAX_INTEGRATE)
+        return fail(h, CORR_E_OVERFLOW, "int8 integration would exceed 66572 spectra since the last reset");
+
+    hipError_t e;
+    const float *s2 = nullptr;
+    if (d_spectra) {
+        e = launch_ingest(h->prec, h->C, h->N, n_spectra, h->n_tb_cap, d_spectra, h->spec, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ingest launch");
+        h->n_held = n_spectra;
+        h->held_from_fengine = false;
+        if (h->prec == P_FP16 || h->prec == P_FP8) {
+            e = launch_scale2(h->C, d_inv_scale, h->scale2_user, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
+            s2 = h->scale2_user;
+        }
+    } else if (h->prec != P_INT8) {
+        s2 = h->held_from_fengine ? h->scale2 : (h->prec == P_FP32 ? nullptr : h->scale2_user);
+    }
+    e = launch_xengine(h->prec, h->C, h->N, n_spectra, h->n_tb_cap, h->spec, s2, h->acc, h->acc_zero ? 1 : 0,
+                       h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
+    h->acc_zero = false;
+    h->n_integrated += n_spectra;
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_dump_visibilities(corr_handle h, void *dst, int32_t dst_on_device, int32_t reset) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (!dst) return fail(h, CORR_E_INVALID_ARG, "dst is NULL");
+    if (dst_on_device && !aligned(dst, 8)) return fail(h, CORR_E_INVALID_ARG, "dst must be 8-byte aligned");
+    const size_t bytes = (size_t)corr_visibility_bytes(&h->p);
+    hipError_t e;
+    if (h->acc_zero) {
+        if (dst_on_device) {
+            e = launch_zero(dst, (int64_t)(bytes / 4), h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "zero launch");
+        } else {
+            e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+            std::memset(dst, 0, bytes);
+        }
+    } else if (default_dump(&h->p)) {
+        e = hipMemcpyAsync(dst, h->acc, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync dump");
+        if (!dst_on_device && (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+            return hip_fail(h, e, "hipStreamSynchronize");
+    } else {
+        void *target = dst;
+        if (!dst_on_device) {
+            if (!h->dump_tmp && (e = hipMalloc(&h->dump_tmp, bytes)) != hipSuccess)
+                return hip_fail(h, e, "hipMalloc dump staging");
+            target = h->dump_tmp;
+        }
+        e = launch_dump_convert(h->C, h->N, h->p.layout, h->p.order, h->prec == P_INT8 ? 1 : 0, h->acc, target,
+                                h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "dump convert launch");
+        if (!dst_on_device) {
+            if ((e = hipMemcpyAsync(dst, target, bytes, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+                return hip_fail(h, e, "hipMemcpyAsync dump");
+            if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+        }
+    }
+    if (reset) {
+        h->acc_zero = true;
+        h->n_integrated = 0;
+    }
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_copy_spectra(corr_handle h, void *dst, int32_t dst_on_device) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (!dst) return fail(h, CORR_E_INVALID_ARG, "dst is NULL");
+    if (h->n_held == 0) return fail(h, CORR_E_STATE, "no spectra held");
+    const size_t bytes = (size_t)corr_spectra_bytes(&h->p, h->n_held);
+    hipError_t e;
+    void *target = dst;
+    void *tmp = nullptr;
+    if (!dst_on_device) {
+        if ((e = hipMalloc(&tmp, bytes)) != hipSuccess) return hip_fail(h, e, "hipMalloc spectra staging");
+        target = tmp;
+    }
+    e = launch_export(h->prec, h->C, h->N, h->n_held, h->n_tb_cap, h->spec, target, h->stream);
+    if (e == hipSuccess && !dst_on_device) {
+        e = hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(h, e, "copy spectra");
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_get_counts(corr_handle h, int32_t *n_held, int64_t *n_integrated) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (!n_held || !n_integrated) return fail(h, CORR_E_INVALID_ARG, "output pointer is NULL");
+    *n_held = h->n_held;
+    *n_integrated = h->n_integrated;
+    return CORR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal declarations shared by the C-ABI layer and the HIP kernels.
+//
+// Spectra buffer layout (device, library-owned), "time-blocked planar":
+//
+//   spec[k][tb][p][plane][TB]      k  : channel            [0, C)
+//                                  tb : time block         [0, n_tb)
+//                                  p  : input              [0, N)
+//                                  plane: 0 = real, 1 = imaginary
+//                                  TB : spectra per block (64 bytes per row)
+//
+// so that, for one channel and one time block, the rows of every input are
+// one contiguous run of N * 128 bytes.  An X-engine tile of 128 inputs reads a
+// contiguous 16 KB slab per time block, and each MFMA fragment (a row's K
+// consecutive spectra of one plane) is a 16-byte vector.  Entries of the last
+// time block beyond the valid spectra are zero, so every block can be
+// correlated whole (zero spectra add nothing to Eq. 2).
+//
+// Accumulator layout (device, library-owned): acc[k][b], b = i(i+1)/2 + j for
+// j <= i, each entry an (re, im) pair of float32 (float forms) or int32 (int8),
+// i.e. the default dump layout, so a default dump is a plain copy.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace corr {
+
+enum Prec : int { P_FP32 = 0, P_FP16 = 1, P_FP8 = 2, P_INT8 = 3 };
+
+// Bytes per (input, plane) row of one time block.
+constexpr int kRowBytes = 64;
+
+inline int elem_bytes(int prec) { return prec == P_FP32 ? 4 : (prec == P_FP16 ? 2 : 1); }
+// Spectra per time block.
+inline int time_block(int prec) { return kRowBytes / elem_bytes(prec); }
+
+// ---- launch entry points (each returns the launch's hipError_t) ----------
+
+// F-engine: C-point FFTs of n_spectra blocks per input, requantised into the
+// time-blocked planar spectra buffer.  Spectra in [n_spectra, n_tb*TB) of the
+// last block are written as zeros.
+hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld,
+                          int n_spectra, const float *inv_scale, const float2 *twiddle,
+                          void *spec, int n_tb_cap, hipStream_t stream);
+
+// X-engine: accumulate Eq. 2 over the first n_spectra spectra of the spectra
+// buffer into acc (spectra past n_spectra in the last time block are masked to
+// zero).  scale2 (float forms, may be null = 1): per-channel s_k^2 applied to
+// the integrated products.  first_call = 1 writes instead of read-modify-write.
+hipError_t launch_xengine(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+                          const float *scale2, void *acc, int first_call, hipStream_t stream);
+
+// Public [A][C][N][2] spectra <-> internal layout (ingest zero-fills the tail
+// of the last time block).
+hipError_t launch_ingest(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *src,
+                         void *spec, hipStream_t stream);
+hipError_t launch_export(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+                         void *dst, hipStream_t stream);
+
+// Dump conversion from the lower-triangle channel-major accumulators into a
+// layout (0 lower, 1 upper, 2 full) and order (0 chan-major, 1 baseline-major).
+// Entries are 8-byte (re, im) pairs; is_int selects int32 negation for the
+// conjugate of mirrored products.
+hipError_t launch_dump_convert(int C, int N, int layout, int order, int is_int,
+                               const void *acc, void *dst, hipStream_t stream);
+
+// s_k^2 = 1 / inv_s[k]^2 (or 1 when inv_s is null) into scale2[C].
+hipError_t launch_scale2(int C, const float *inv_scale, float *scale2, hipStream_t stream);
+
+// Fill n 32-bit words with zero (a kernel, not a memset node, so the call is
+// safe inside captured graphs).
+hipError_t launch_zero(void *p, int64_t n_words, hipStream_t stream);
+
+}  // namespace corr

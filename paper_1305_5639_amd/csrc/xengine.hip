@@ -1,0 +1,337 @@
+// X-engine: the correlation of Section 2, Eq. 2, over the triangle of
+// non-redundant input pairs (Section 4), as a batched Hermitian rank-A update
+// on MFMA:  for each channel k,  C_k += X_k^H X_k,  X_k = [A spectra x N inputs].
+//
+// Complex arithmetic on real MFMA.  With x = xr + j xi,
+//   Re C_ij = sum_a xr_i xr_j + xi_i xi_j
+//   Im C_ij = sum_a xr_i xi_j - xi_i xr_j
+// so each 32x32 output block takes four real MFMAs per K step:
+//   re += Ar*Br, re += Ai*Bi, im += Ar*Bi, im += Ai*(-Br),
+// where A holds rows i (the conjugated input) and B columns j.  The negated
+// operand is formed in registers (sign flip for float forms, a byte-wise SWAR
+// negate for int8, exact because the int8 range is symmetric).
+//
+// Tiling.  A workgroup (256 threads, 4 waves) owns a 128x128 block (rows I,
+// columns J <= I) of one channel; each wave a 64x64 quarter as 2x2 MFMA
+// 32x32 blocks with separate real and imaginary accumulators.  On diagonal
+// blocks the wave above the diagonal idles and the diagonal waves skip their
+// upper 32x32 block.  The K loop walks time blocks: each stage copies the
+// rows' contiguous 16 KB slab (128 inputs x 2 planes x 64 bytes) for I and J
+// from global memory into padded LDS rows (144-byte stride, conflict-free
+// 16-byte fragment reads), double-buffered with one barrier per stage.
+// Every lane reads 32 bytes per (fragment, plane) per stage, which is one K
+// step for FP8 (32x32x64), two for int8 (32x32x32) and FP16 (32x32x16), and
+// eight for FP32 (32x32x2).  Because the same K assignment is used for both
+// operands, the spectrum-to-slot order inside a stage does not matter.
+//
+// Workgroups map XCD-major (each XCD takes a contiguous range of
+// (channel, block) items) so one channel's blocks share an L2.
+// The epilogue scales by s_k^2 (float forms) and adds into the persistent
+// lower-triangle accumulators (or writes them on the first call of an
+// integration); autos get an exactly zero imaginary part, as Eq. 2 gives.
+#include "corr_internal.h"
+
+namespace corr {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kXThreads = 256;
+constexpr int kTile = 128;
+constexpr int kRowStride = 144;                   // 2 planes x 64 B + 16 B pad
+constexpr int kOpBytes = kTile * kRowStride;
+constexpr int kStageBytes = 2 * kOpBytes;
+
+template <int PREC> struct XT;
+
+template <> struct XT<P_FP32> {
+    using Acc = f32x16;
+    static constexpr uint32_t kSign = 0x80000000u;
+    static __device__ __forceinline__ i32x8 neg(i32x8 b) {
+        i32x8 r;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) r[t] = b[t] ^ (int)kSign;
+        return r;
+    }
+    static __device__ __forceinline__ void mma(Acc &re, Acc &im, const i32x8 &ar, const i32x8 &ai,
+                                               const i32x8 &br, const i32x8 &bi, const i32x8 &nbr) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            re = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(ar[s]), __int_as_float(br[s]), re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(ar[s]), __int_as_float(bi[s]), im, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(ai[s]), __int_as_float(bi[s]), re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(ai[s]), __int_as_float(nbr[s]), im, 0, 0, 0);
+        }
+    }
+};
+
+__device__ __forceinline__ i32x4 lo4(const i32x8 &x) { return i32x4{x[0], x[1], x[2], x[3]}; }
+__device__ __forceinline__ i32x4 hi4(const i32x8 &x) { return i32x4{x[4], x[5], x[6], x[7]}; }
+__device__ __forceinline__ f16x8 as_h8(const i32x4 &x) { return __builtin_bit_cast(f16x8, x); }
+
+template <> struct XT<P_FP16> {
+    using Acc = f32x16;
+    static __device__ __forceinline__ i32x8 neg(i32x8 b) {
+        i32x8 r;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) r[t] = b[t] ^ (int)0x80008000u;
+        return r;
+    }
+    static __device__ __forceinline__ void step(Acc &re, Acc &im, const i32x4 &ar, const i32x4 &ai,
+                                                const i32x4 &br, const i32x4 &bi, const i32x4 &nbr) {
+        re = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_h8(ar), as_h8(br), re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_h8(ar), as_h8(bi), im, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_h8(ai), as_h8(bi), re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_h8(ai), as_h8(nbr), im, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void mma(Acc &re, Acc &im, const i32x8 &ar, const i32x8 &ai,
+                                               const i32x8 &br, const i32x8 &bi, const i32x8 &nbr) {
+        step(re, im, lo4(ar), lo4(ai), lo4(br), lo4(bi), lo4(nbr));
+        step(re, im, hi4(ar), hi4(ai), hi4(br), hi4(bi), hi4(nbr));
+    }
+};
+
+template <> struct XT<P_INT8> {
+    using Acc = i32x16;
+    // Byte-wise 0 - b without borrows between bytes.
+    static __device__ __forceinline__ i32x8 neg(i32x8 b) {
+        i32x8 r;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const uint32_t x = (uint32_t)b[t];
+            r[t] = (int)((0x80808080u - (x & 0x7f7f7f7fu)) ^ (~x & 0x80808080u));
+        }
+        return r;
+    }
+    static __device__ __forceinline__ void step(Acc &re, Acc &im, const i32x4 &ar, const i32x4 &ai,
+                                                const i32x4 &br, const i32x4 &bi, const i32x4 &nbr) {
+        re = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, br, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, bi, im, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai, bi, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai, nbr, im, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void mma(Acc &re, Acc &im, const i32x8 &ar, const i32x8 &ai,
+                                               const i32x8 &br, const i32x8 &bi, const i32x8 &nbr) {
+        step(re, im, lo4(ar), lo4(ai), lo4(br), lo4(bi), lo4(nbr));
+        step(re, im, hi4(ar), hi4(ai), hi4(br), hi4(bi), hi4(nbr));
+    }
+};
+
+template <> struct XT<P_FP8> {
+    using Acc = f32x16;
+    static __device__ __forceinline__ i32x8 neg(i32x8 b) {
+        i32x8 r;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) r[t] = b[t] ^ (int)0x80808080u;
+        return r;
+    }
+    // Format code 0 = FP8 E4M3 for both operands; E8M0 scale 127 = 2^0.
+    static __device__ __forceinline__ void mma(Acc &re, Acc &im, const i32x8 &ar, const i32x8 &ai,
+                                               const i32x8 &br, const i32x8 &bi, const i32x8 &nbr) {
+        re = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ar, br, re, 0, 0, 0, 127, 0, 127);
+        im = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ar, bi, im, 0, 0, 0, 127, 0, 127);
+        re = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ai, bi, re, 0, 0, 0, 127, 0, 127);
+        im = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ai, nbr, im, 0, 0, 0, 127, 0, 127);
+    }
+};
+
+__device__ __forceinline__ i32x8 lds_read32(const uint8_t *p) {
+    const i32x4 a = *reinterpret_cast<const i32x4 *>(p);
+    const i32x4 b = *reinterpret_cast<const i32x4 *>(p + 16);
+    return i32x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kXThreads) void xengine_kernel(
+    const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
+    int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, int64_t B,
+    int first_call) {
+    using Acc = typename XT<PREC>::Acc;
+    constexpr int ES = PREC == P_FP32 ? 4 : (PREC == P_FP16 ? 2 : 1);
+    constexpr int TB = kRowBytes / ES;
+    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * kStageBytes];
+
+    const int tid = threadIdx.x;
+    const int per = (n_work + 7) / 8;
+    const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (w >= n_work) return;
+    const int k = w / n_tiles;
+    const int t = w % n_tiles;
+    int bi = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (bi * (bi + 1) / 2 > t) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const bool diag = bi == bj;
+    const int I0 = bi * kTile, J0 = bj * kTile;
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int m = lane & 31, h = lane >> 5;
+    const bool active = !(diag && wj > wi);
+    const bool dwave = diag && wi == wj;     // diagonal wave: skip its upper 32x32 block
+
+    const uint8_t *base_k = spec + (int64_t)k * k_stride;
+
+    uint4 st[8];
+    auto load_stage = [&](int tb) {
+        const uint8_t *blk = base_k + (int64_t)tb * N * (2 * kRowBytes);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = tid + kXThreads * u;
+            const int row = c >> 3, col = c & 7;
+            const int pI = I0 + row;
+            st[u] = pI < N ? *reinterpret_cast<const uint4 *>(blk + (int64_t)pI * (2 * kRowBytes) + col * 16)
+                           : make_uint4(0, 0, 0, 0);
+            if (!diag) {
+                const int pJ = J0 + row;
+                st[4 + u] = pJ < N ? *reinterpret_cast<const uint4 *>(blk + (int64_t)pJ * (2 * kRowBytes) + col * 16)
+                                   : make_uint4(0, 0, 0, 0);
+            }
+        }
+        if (tb == n_tb - 1 && tv < TB) {
+            // zero the spectra past the valid count in the last time block
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = tid + kXThreads * (u & 3);
+                const int off = ((c & 7) & 3) * 16;
+                uint32_t *wd = reinterpret_cast<uint32_t *>(&st[u]);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    uint32_t msk = 0;
+#pragma unroll
+                    for (int bb = 0; bb < 4; ++bb)
+                        if ((off + 4 * d + bb) / ES < tv) msk |= 0xffu << (8 * bb);
+                    wd[d] &= msk;
+                }
+            }
+        }
+    };
+    auto store_stage = [&](int buf) {
+        uint8_t *s = smem + buf * kStageBytes;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = tid + kXThreads * u;
+            const int row = c >> 3, col = c & 7;
+            *reinterpret_cast<uint4 *>(s + row * kRowStride + col * 16) = st[u];
+            if (!diag) *reinterpret_cast<uint4 *>(s + kOpBytes + row * kRowStride + col * 16) = st[4 + u];
+        }
+    };
+
+    Acc re[2][2], im[2][2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                re[f][g][r] = 0;
+                im[f][g][r] = 0;
+            }
+        }
+
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+    for (int tb = 0; tb < n_tb; ++tb) {
+        const bool more = tb + 1 < n_tb;
+        if (more) load_stage(tb + 1);
+        if (active) {
+            const uint8_t *sI = smem + (tb & 1) * kStageBytes;
+            const uint8_t *sJ = diag ? sI : sI + kOpBytes;
+            i32x8 a[2][2], b[2][2], nb[2];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const uint8_t *pa = sI + (wi * 64 + f * 32 + m) * kRowStride + h * 32;
+                a[f][0] = lds_read32(pa);
+                a[f][1] = lds_read32(pa + kRowBytes);
+                const uint8_t *pb = sJ + (wj * 64 + f * 32 + m) * kRowStride + h * 32;
+                b[f][0] = lds_read32(pb);
+                b[f][1] = lds_read32(pb + kRowBytes);
+                nb[f] = XT<PREC>::neg(b[f][0]);
+            }
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    if (dwave && f < g) continue;
+                    XT<PREC>::mma(re[f][g], im[f][g], a[f][0], a[f][1], b[g][0], b[g][1], nb[g]);
+                }
+        }
+        if (more) store_stage((tb + 1) & 1);
+        __syncthreads();
+    }
+    if (!active) return;
+
+    // Epilogue: 32x32 block element (row 8(r/4) + 4h + r%4, column m).
+    const float s2 = (PREC != P_INT8 && scale2) ? scale2[k] : 1.0f;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            if (dwave && f < g) continue;
+            const int j = J0 + wj * 64 + g * 32 + m;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = I0 + wi * 64 + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                if (i >= N || j > i) continue;
+                const int64_t idx = (int64_t)k * B + (int64_t)i * (i + 1) / 2 + j;
+                if constexpr (PREC == P_INT8) {
+                    int2 v = make_int2(re[f][g][r], i == j ? 0 : im[f][g][r]);
+                    int2 *o = reinterpret_cast<int2 *>(acc_out) + idx;
+                    if (!first_call) {
+                        const int2 old = *o;
+                        v.x += old.x;
+                        v.y += old.y;
+                    }
+                    *o = v;
+                } else {
+                    float2 v = make_float2(re[f][g][r] * s2, i == j ? 0.0f : im[f][g][r] * s2);
+                    float2 *o = reinterpret_cast<float2 *>(acc_out) + idx;
+                    if (!first_call) {
+                        const float2 old = *o;
+                        v.x += old.x;
+                        v.y += old.y;
+                    }
+                    *o = v;
+                }
+            }
+        }
+}
+
+template <int PREC>
+hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
+                    void *acc, int first_call, hipStream_t stream) {
+    const int TB = time_block(PREC);
+    const int n_tb = (n_spectra + TB - 1) / TB;
+    const int tv = n_spectra - (n_tb - 1) * TB;
+    const int n_blk = (N + kTile - 1) / kTile;
+    const int n_tiles = n_blk * (n_blk + 1) / 2;
+    const int64_t n_work = (int64_t)C * n_tiles;
+    if (n_tb <= 0 || n_work <= 0 || n_work > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+    const int grid = (int)((n_work + 7) / 8) * 8;
+    const int64_t k_stride = (int64_t)n_tb_cap * N * (2 * kRowBytes);
+    const int64_t B = (int64_t)N * (N + 1) / 2;
+    hipLaunchKernelGGL(xengine_kernel<PREC>, dim3(grid), dim3(kXThreads), 0, stream,
+                       static_cast<const uint8_t *>(spec), N, n_tiles, (int)n_work, n_tb, tv, k_stride,
+                       scale2, acc, B, first_call);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_xengine(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+                          const float *scale2, void *acc, int first_call, hipStream_t stream) {
+    switch (prec) {
+    case P_FP32: return launch_x<P_FP32>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    case P_FP16: return launch_x<P_FP16>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    case P_FP8: return launch_x<P_FP8>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    case P_INT8: return launch_x<P_INT8>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace corr

@@ -1,0 +1,142 @@
+"""The C ABI on the CPU: the library loads, exports every function the header
+declares, and decides every argument, budget and overflow error before any
+HIP call (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1305_5639_amd as corr
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "corr.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"CORR_API\s+[\w\s\*]+?\b(corr_\w+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared() == sorted(corr.ABI_FUNCTIONS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = corr.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    # only the C ABI is exported
+    out = os.popen(f"nm -D --defined-only {corr.LIB_PATH}").read()
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert exported == set(_declared())
+
+
+def test_header_enum_values_match_binding():
+    txt = open(HEADER).read()
+    for name in ("CORR_OK", "CORR_E_INVALID_ARG", "CORR_E_UNSUPPORTED", "CORR_E_NOMEM",
+                 "CORR_E_OVERFLOW", "CORR_E_STATE", "CORR_E_HIP", "CORR_FP32", "CORR_FP16",
+                 "CORR_FP8_E4M3", "CORR_INT8", "CORR_TRI_LOWER", "CORR_TRI_UPPER", "CORR_FULL",
+                 "CORR_CHAN_MAJOR", "CORR_BASELINE_MAJOR"):
+        m = re.search(rf"\b{name}\s*=\s*(\d+)", txt)
+        assert m and int(m.group(1)) == getattr(corr, name), name
+    for name in ("CORR_INT8_MAX_INTEGRATE",):
+        m = re.search(rf"#define\s+{name}\s+(\d+)", txt)
+        assert int(m.group(1)) == getattr(corr, name)
+    assert ctypes.sizeof(corr.corr_params) == 40
+
+
+def test_int8_overflow_limit_is_the_int32_bound():
+    """2 * 127^2 * A must fit int32: A <= 66572."""
+    assert 2 * 127 * 127 * corr.CORR_INT8_MAX_INTEGRATE <= 2 ** 31 - 1
+    assert 2 * 127 * 127 * (corr.CORR_INT8_MAX_INTEGRATE + 1) > 2 ** 31 - 1
+
+
+def test_sizes():
+    p = corr.make_params(128, 2, 1024, 1000, "fp32")
+    assert corr.corr_n_products(p) == 32896
+    assert corr.corr_visibility_bytes(p) == 32896 * 1024 * 8
+    assert corr.corr_spectra_bytes(p, 10) == 10 * 1024 * 256 * 2 * 4
+    p = corr.make_params(16, 1, 64, 1024, "int8", layout="full")
+    assert corr.corr_n_products(p) == 136
+    assert corr.corr_visibility_bytes(p) == 256 * 64 * 8
+    assert corr.corr_spectra_bytes(p, 3) == 3 * 64 * 16 * 2
+    assert corr.corr_n_products(corr.make_params(0, 1, 64, 1)) == -1
+
+
+def _create_status(**kw):
+    base = dict(n_stations=4, n_pols=2, n_channels=64, n_integrate=16, precision="fp32",
+                layout="lower", order="chan", device_mem_cap=1 << 40)
+    base.update(kw)
+    p = corr.make_params(**base)
+    h = ctypes.c_void_p()
+    return corr.lib().corr_create(ctypes.byref(p), None, ctypes.byref(h)), h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_stations=0), corr.CORR_E_INVALID_ARG),
+    (dict(n_pols=3), corr.CORR_E_INVALID_ARG),
+    (dict(n_pols=0), corr.CORR_E_INVALID_ARG),
+    (dict(n_channels=48), corr.CORR_E_INVALID_ARG),
+    (dict(n_channels=0), corr.CORR_E_INVALID_ARG),
+    (dict(n_channels=8), corr.CORR_E_UNSUPPORTED),
+    (dict(n_channels=16384), corr.CORR_E_UNSUPPORTED),
+    (dict(n_integrate=0), corr.CORR_E_INVALID_ARG),
+    (dict(precision=7), corr.CORR_E_INVALID_ARG),
+    (dict(layout=5), corr.CORR_E_INVALID_ARG),
+    (dict(order=2), corr.CORR_E_INVALID_ARG),
+    (dict(n_stations=4097, n_pols=2), corr.CORR_E_UNSUPPORTED),
+    (dict(precision="int8", n_integrate=66573), corr.CORR_E_OVERFLOW),
+    (dict(device_mem_cap=1000), corr.CORR_E_NOMEM),
+])
+def test_create_rejects_on_cpu(kw, status):
+    s, h = _create_status(**kw)
+    assert s == status
+    assert h.value is None                      # output written only on success
+    assert corr.corr_last_error(None) != ""
+
+
+def test_nomem_budget_is_exact():
+    """The budget counts spectra, accumulators, twiddles and scales."""
+    N, C, A = 8, 64, 16
+    spec = C * ((A + 15) // 16) * N * 2 * 64
+    acc = C * N * (N + 1) // 2 * 8
+    small = C * 8 + 2 * C * 4
+    s, _ = _create_status(device_mem_cap=spec + acc + small - 1)
+    assert s == corr.CORR_E_NOMEM
+    # a non-default layout also needs dump staging
+    s, _ = _create_status(layout="full", device_mem_cap=spec + acc + small + 1)
+    assert s == corr.CORR_E_NOMEM
+
+
+def test_int8_limit_accepted():
+    p = corr.make_params(1, 1, 16, corr.CORR_INT8_MAX_INTEGRATE, "int8", device_mem_cap=1000)
+    h = ctypes.c_void_p()
+    # passes the overflow check, then fails the (CPU-side) budget
+    assert corr.lib().corr_create(ctypes.byref(p), None, ctypes.byref(h)) == corr.CORR_E_NOMEM
+
+
+def test_null_arguments():
+    L = corr.lib()
+    h = ctypes.c_void_p()
+    assert L.corr_create(None, None, ctypes.byref(h)) == corr.CORR_E_INVALID_ARG
+    p = corr.make_params(2, 1, 16, 4)
+    assert L.corr_create(ctypes.byref(p), None, None) == corr.CORR_E_INVALID_ARG
+    assert L.corr_destroy(None) == corr.CORR_E_INVALID_ARG
+    assert L.corr_fengine(None, None, 0, 0, None) == corr.CORR_E_INVALID_ARG
+    assert L.corr_xengine(None, None, 1, None) == corr.CORR_E_INVALID_ARG
+    assert L.corr_dump_visibilities(None, None, 0, 0) == corr.CORR_E_INVALID_ARG
+    assert L.corr_copy_spectra(None, None, 0) == corr.CORR_E_INVALID_ARG
+    a, b = ctypes.c_int32(), ctypes.c_int64()
+    assert L.corr_get_counts(None, ctypes.byref(a), ctypes.byref(b)) == corr.CORR_E_INVALID_ARG
+
+
+def test_status_strings():
+    for s in range(7):
+        assert corr.corr_status_string(s).startswith("CORR_")
+    assert "unknown" in corr.corr_status_string(42)
+
+
+def test_error_raises_with_status():
+    with pytest.raises(corr.CorrError) as ei:
+        corr.corr_create(corr.make_params(3, 5, 64, 8))
+    assert ei.value.status == corr.CORR_E_INVALID_ARG
