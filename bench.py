@@ -52,6 +52,8 @@ def parse():
                     help="other precisions to time on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "xengine_traffic.json"),
                     help="HBM bytes per X-engine launch measured with rocprofv3 counters")
     return ap.parse_args()
@@ -169,6 +171,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # A plain copy of known size: 1 GiB read + 1 GiB written per launch.
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 1 GiB device-to-device (elementwise copy kernel)")
+        del src, dst
     w = synth.WORKLOADS[args.workload]
     N, C, A = w.n_inputs, w.n_channels, w.n_integrate
     B = N * (N + 1) // 2

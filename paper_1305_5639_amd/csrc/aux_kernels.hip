@@ -16,6 +16,7 @@ template <typename T>
 __global__ void ingest_kernel(const T *__restrict__ src, T *__restrict__ spec, int C, int N, int n_spectra,
                               int n_tb, int n_tb_cap) {
     constexpr int TB = kRowBytes / (int)sizeof(T);
+    const int64_t k_stride = channel_stride(n_tb_cap, N) / (int64_t)sizeof(T);
     const int64_t total = (int64_t)C * n_tb * N * 2 * TB;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -29,7 +30,7 @@ __global__ void ingest_kernel(const T *__restrict__ src, T *__restrict__ spec, i
         const int k = (int)(r / n_tb);
         const int a = tb * TB + t;
         const T v = a < n_spectra ? src[(((int64_t)a * C + k) * N + p) * 2 + pl] : zero_of<T>();
-        spec[((((int64_t)k * n_tb_cap + tb) * N + p) * 2 + pl) * TB + t] = v;
+        spec[k * k_stride + (((int64_t)tb * N + p) * 2 + pl) * TB + t] = v;
     }
 }
 
@@ -38,6 +39,7 @@ template <typename T>
 __global__ void export_kernel(const T *__restrict__ spec, T *__restrict__ dst, int C, int N, int n_spectra,
                               int n_tb_cap) {
     constexpr int TB = kRowBytes / (int)sizeof(T);
+    const int64_t k_stride = channel_stride(n_tb_cap, N) / (int64_t)sizeof(T);
     const int64_t total = (int64_t)n_spectra * C * N * 2;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -48,7 +50,7 @@ __global__ void export_kernel(const T *__restrict__ spec, T *__restrict__ dst, i
         const int k = (int)(r % C);
         const int a = (int)(r / C);
         const int tb = a / TB, t = a % TB;
-        dst[e] = spec[((((int64_t)k * n_tb_cap + tb) * N + p) * 2 + pl) * TB + t];
+        dst[e] = spec[k * k_stride + (((int64_t)tb * N + p) * 2 + pl) * TB + t];
     }
 }
 

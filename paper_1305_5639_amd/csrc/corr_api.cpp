@@ -171,7 +171,7 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
     const int prec = params->precision;
     const int TB = time_block(prec);
     const int n_tb_cap = (params->n_integrate + TB - 1) / TB;
-    const size_t spec_bytes = (size_t)C * n_tb_cap * N * 2 * kRowBytes;
+    const size_t spec_bytes = (size_t)C * (size_t)channel_stride(n_tb_cap, N);
     const int64_t B = (int64_t)N * (N + 1) / 2;
     const size_t acc_bytes = (size_t)C * B * 8;
     const size_t small_bytes = (size_t)C * 8 + 2 * (size_t)C * 4;

@@ -2,7 +2,8 @@
 //
 // Spectra buffer layout (device, library-owned), "time-blocked planar":
 //
-//   spec[k][tb][p][plane][TB]      k  : channel            [0, C)
+//   spec[k][tb][p][plane][TB]      k  : channel            [0, C), stride
+//                                       channel_stride() bytes
 //                                  tb : time block         [0, n_tb)
 //                                  p  : input              [0, N)
 //                                  plane: 0 = real, 1 = imaginary
@@ -29,6 +30,15 @@ enum Prec : int { P_FP32 = 0, P_FP16 = 1, P_FP8 = 2, P_INT8 = 3 };
 
 // Bytes per (input, plane) row of one time block.
 constexpr int kRowBytes = 64;
+// Bytes added after each channel's slab of the spectra buffer.  Without it
+// the channel stride is a large power of two and the F-engine's transposing
+// stores (one per channel) all land in the same HBM channel.
+constexpr int kChannelPad = 256;
+
+// Byte stride between channels of the spectra buffer.
+__host__ __device__ inline int64_t channel_stride(int n_tb_cap, int N) {
+    return (int64_t)n_tb_cap * N * 2 * kRowBytes + kChannelPad;
+}
 
 inline int elem_bytes(int prec) { return prec == P_FP32 ? 4 : (prec == P_FP16 ? 2 : 1); }
 // Spectra per time block.

@@ -104,10 +104,22 @@ __device__ __forceinline__ void pass_compute(float2 *v, const float2 *__restrict
         if constexpr (NS > 1) {
             int t, j;
             bfly_index<C, T, R, REMAP>(tid + kThreads * q, t, j);
-            const int jm = j % NS;
+            const int m = (j % NS) * (C / (NS * R));
+            if constexpr (R == 8) {
+                // three table reads, the other powers by products (depth <= 2)
+                const float2 w1 = tw[m], w2 = tw[2 * m], w4 = tw[4 * m];
+                const float2 w3 = cmul(w1, w2);
+                v[q * R + 1] = cmul(v[q * R + 1], w1);
+                v[q * R + 2] = cmul(v[q * R + 2], w2);
+                v[q * R + 3] = cmul(v[q * R + 3], w3);
+                v[q * R + 4] = cmul(v[q * R + 4], w4);
+                v[q * R + 5] = cmul(v[q * R + 5], cmul(w1, w4));
+                v[q * R + 6] = cmul(v[q * R + 6], cmul(w2, w4));
+                v[q * R + 7] = cmul(v[q * R + 7], cmul(w3, w4));
+            } else {
 #pragma unroll
-            for (int r = 1; r < R; ++r)
-                v[q * R + r] = cmul(v[q * R + r], tw[r * jm * (C / (NS * R))]);
+                for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], tw[r * m]);
+            }
         }
         dft<R>(v + q * R);
     }
@@ -271,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(
     using V = typename Bytes<CH>::T;
     constexpr int CPR = S / CH;                        // chunks per staged row
     constexpr int NCH = 2 * C * CPR;
-    const int64_t k_stride = (int64_t)n_tb_cap * N * kRowBytes * 2;
+    const int64_t k_stride = channel_stride(n_tb_cap, N);
     for (int c = tid; c < NCH; c += kThreads) {
         const int row = c / CPR, x = c % CPR;
         const int pl = row / C, k = row % C;

@@ -46,107 +46,75 @@ constexpr int kRowStride = 144;                   // 2 planes x 64 B + 16 B pad
 constexpr int kOpBytes = kTile * kRowStride;
 constexpr int kStageBytes = 2 * kOpBytes;
 
+// Per-precision fragment type and MFMA step.  A lane owns 32 bytes of each
+// (row, plane) per time block; KS MFMA K steps consume them, FB bytes each.
 template <int PREC> struct XT;
 
 template <> struct XT<P_FP32> {
     using Acc = f32x16;
-    static constexpr uint32_t kSign = 0x80000000u;
-    static __device__ __forceinline__ i32x8 neg(i32x8 b) {
-        i32x8 r;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) r[t] = b[t] ^ (int)kSign;
-        return r;
-    }
-    static __device__ __forceinline__ void mma(Acc &re, Acc &im, const i32x8 &ar, const i32x8 &ai,
-                                               const i32x8 &br, const i32x8 &bi, const i32x8 &nbr) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            re = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(ar[s]), __int_as_float(br[s]), re, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(ar[s]), __int_as_float(bi[s]), im, 0, 0, 0);
-            re = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(ai[s]), __int_as_float(bi[s]), re, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(ai[s]), __int_as_float(nbr[s]), im, 0, 0, 0);
-        }
+    using Frag = float;
+    static constexpr int KS = 8, FB = 4;
+    static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const float *>(p); }
+    static __device__ __forceinline__ Frag neg(Frag b) { return -b; }
+    static __device__ __forceinline__ void mfma(Acc &c, Frag a, Frag b) {
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
     }
 };
 
-__device__ __forceinline__ i32x4 lo4(const i32x8 &x) { return i32x4{x[0], x[1], x[2], x[3]}; }
-__device__ __forceinline__ i32x4 hi4(const i32x8 &x) { return i32x4{x[4], x[5], x[6], x[7]}; }
-__device__ __forceinline__ f16x8 as_h8(const i32x4 &x) { return __builtin_bit_cast(f16x8, x); }
-
 template <> struct XT<P_FP16> {
     using Acc = f32x16;
-    static __device__ __forceinline__ i32x8 neg(i32x8 b) {
-        i32x8 r;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) r[t] = b[t] ^ (int)0x80008000u;
-        return r;
+    using Frag = i32x4;
+    static constexpr int KS = 2, FB = 16;
+    static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const i32x4 *>(p); }
+    static __device__ __forceinline__ Frag neg(Frag b) {
+        return Frag{b[0] ^ (int)0x80008000u, b[1] ^ (int)0x80008000u, b[2] ^ (int)0x80008000u,
+                    b[3] ^ (int)0x80008000u};
     }
-    static __device__ __forceinline__ void step(Acc &re, Acc &im, const i32x4 &ar, const i32x4 &ai,
-                                                const i32x4 &br, const i32x4 &bi, const i32x4 &nbr) {
-        re = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_h8(ar), as_h8(br), re, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_h8(ar), as_h8(bi), im, 0, 0, 0);
-        re = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_h8(ai), as_h8(bi), re, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_h8(ai), as_h8(nbr), im, 0, 0, 0);
-    }
-    static __device__ __forceinline__ void mma(Acc &re, Acc &im, const i32x8 &ar, const i32x8 &ai,
-                                               const i32x8 &br, const i32x8 &bi, const i32x8 &nbr) {
-        step(re, im, lo4(ar), lo4(ai), lo4(br), lo4(bi), lo4(nbr));
-        step(re, im, hi4(ar), hi4(ai), hi4(br), hi4(bi), hi4(nbr));
+    static __device__ __forceinline__ f16x8 h8(Frag x) { return __builtin_bit_cast(f16x8, x); }
+    static __device__ __forceinline__ void mfma(Acc &c, Frag a, Frag b) {
+        c = __builtin_amdgcn_mfma_f32_32x32x16_f16(h8(a), h8(b), c, 0, 0, 0);
     }
 };
 
 template <> struct XT<P_INT8> {
     using Acc = i32x16;
+    using Frag = i32x4;
+    static constexpr int KS = 2, FB = 16;
+    static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const i32x4 *>(p); }
     // Byte-wise 0 - b without borrows between bytes.
-    static __device__ __forceinline__ i32x8 neg(i32x8 b) {
-        i32x8 r;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const uint32_t x = (uint32_t)b[t];
-            r[t] = (int)((0x80808080u - (x & 0x7f7f7f7fu)) ^ (~x & 0x80808080u));
-        }
-        return r;
+    static __device__ __forceinline__ int neg4(int v) {
+        const uint32_t x = (uint32_t)v;
+        return (int)((0x80808080u - (x & 0x7f7f7f7fu)) ^ (~x & 0x80808080u));
     }
-    static __device__ __forceinline__ void step(Acc &re, Acc &im, const i32x4 &ar, const i32x4 &ai,
-                                                const i32x4 &br, const i32x4 &bi, const i32x4 &nbr) {
-        re = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, br, re, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar, bi, im, 0, 0, 0);
-        re = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai, bi, re, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_i32_32x32x32_i8(ai, nbr, im, 0, 0, 0);
-    }
-    static __device__ __forceinline__ void mma(Acc &re, Acc &im, const i32x8 &ar, const i32x8 &ai,
-                                               const i32x8 &br, const i32x8 &bi, const i32x8 &nbr) {
-        step(re, im, lo4(ar), lo4(ai), lo4(br), lo4(bi), lo4(nbr));
-        step(re, im, hi4(ar), hi4(ai), hi4(br), hi4(bi), hi4(nbr));
+    static __device__ __forceinline__ Frag neg(Frag b) { return Frag{neg4(b[0]), neg4(b[1]), neg4(b[2]), neg4(b[3])}; }
+    static __device__ __forceinline__ void mfma(Acc &c, Frag a, Frag b) {
+        c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
     }
 };
 
 template <> struct XT<P_FP8> {
     using Acc = f32x16;
-    static __device__ __forceinline__ i32x8 neg(i32x8 b) {
-        i32x8 r;
+    using Frag = i32x8;
+    static constexpr int KS = 1, FB = 32;
+    static __device__ __forceinline__ Frag load(const uint8_t *p) {
+        const i32x4 a = *reinterpret_cast<const i32x4 *>(p);
+        const i32x4 b = *reinterpret_cast<const i32x4 *>(p + 16);
+        return Frag{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    }
+    static __device__ __forceinline__ Frag neg(Frag b) {
+        Frag r;
 #pragma unroll
         for (int t = 0; t < 8; ++t) r[t] = b[t] ^ (int)0x80808080u;
         return r;
     }
     // Format code 0 = FP8 E4M3 for both operands; E8M0 scale 127 = 2^0.
-    static __device__ __forceinline__ void mma(Acc &re, Acc &im, const i32x8 &ar, const i32x8 &ai,
-                                               const i32x8 &br, const i32x8 &bi, const i32x8 &nbr) {
-        re = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ar, br, re, 0, 0, 0, 127, 0, 127);
-        im = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ar, bi, im, 0, 0, 0, 127, 0, 127);
-        re = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ai, bi, re, 0, 0, 0, 127, 0, 127);
-        im = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ai, nbr, im, 0, 0, 0, 127, 0, 127);
+    static __device__ __forceinline__ void mfma(Acc &c, Frag a, Frag b) {
+        c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
     }
 };
 
-__device__ __forceinline__ i32x8 lds_read32(const uint8_t *p) {
-    const i32x4 a = *reinterpret_cast<const i32x4 *>(p);
-    const i32x4 b = *reinterpret_cast<const i32x4 *>(p + 16);
-    return i32x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-}
-
 template <int PREC>
-__global__ __launch_bounds__(kXThreads) void xengine_kernel(
+__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void xengine_kernel(
     const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
     int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, int64_t B,
     int first_call) {
@@ -240,26 +208,39 @@ __global__ __launch_bounds__(kXThreads) void xengine_kernel(
         const bool more = tb + 1 < n_tb;
         if (more) load_stage(tb + 1);
         if (active) {
+            using X = XT<PREC>;
             const uint8_t *sI = smem + (tb & 1) * kStageBytes;
             const uint8_t *sJ = diag ? sI : sI + kOpBytes;
-            i32x8 a[2][2], b[2][2], nb[2];
+            const uint8_t *pa = sI + (wi * 64 + m) * kRowStride + h * 32;
+            const uint8_t *pb = sJ + (wj * 64 + m) * kRowStride + h * 32;
 #pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                const uint8_t *pa = sI + (wi * 64 + f * 32 + m) * kRowStride + h * 32;
-                a[f][0] = lds_read32(pa);
-                a[f][1] = lds_read32(pa + kRowBytes);
-                const uint8_t *pb = sJ + (wj * 64 + f * 32 + m) * kRowStride + h * 32;
-                b[f][0] = lds_read32(pb);
-                b[f][1] = lds_read32(pb + kRowBytes);
-                nb[f] = XT<PREC>::neg(b[f][0]);
-            }
-#pragma unroll
-            for (int f = 0; f < 2; ++f)
+            for (int s = 0; s < X::KS; ++s) {
+                // B fragments (columns j) for both 32-column halves, then each
+                // 32-row half of A in turn; the four real products of a block
+                // are issued across both halves so dependent MFMAs are apart.
+                typename X::Frag b[2][2], nb[2];
 #pragma unroll
                 for (int g = 0; g < 2; ++g) {
-                    if (dwave && f < g) continue;
-                    XT<PREC>::mma(re[f][g], im[f][g], a[f][0], a[f][1], b[g][0], b[g][1], nb[g]);
+                    b[g][0] = X::load(pb + g * 32 * kRowStride + s * X::FB);
+                    b[g][1] = X::load(pb + g * 32 * kRowStride + kRowBytes + s * X::FB);
+                    nb[g] = X::neg(b[g][0]);
                 }
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    const typename X::Frag ar = X::load(pa + f * 32 * kRowStride + s * X::FB);
+                    const typename X::Frag ai = X::load(pa + f * 32 * kRowStride + kRowBytes + s * X::FB);
+                    // a diagonal wave skips its upper block (f = 0, g = 1)
+                    const bool up = dwave && f == 0;
+                    X::mfma(re[f][0], ar, b[0][0]);                 // + xr_i xr_j
+                    if (!up) X::mfma(re[f][1], ar, b[1][0]);
+                    X::mfma(im[f][0], ar, b[0][1]);                 // + xr_i xi_j
+                    if (!up) X::mfma(im[f][1], ar, b[1][1]);
+                    X::mfma(re[f][0], ai, b[0][1]);                 // + xi_i xi_j
+                    if (!up) X::mfma(re[f][1], ai, b[1][1]);
+                    X::mfma(im[f][0], ai, nb[0]);                   // - xi_i xr_j
+                    if (!up) X::mfma(im[f][1], ai, nb[1]);
+                }
+            }
         }
         if (more) store_stage((tb + 1) & 1);
         __syncthreads();
@@ -313,7 +294,7 @@ hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec,
     const int64_t n_work = (int64_t)C * n_tiles;
     if (n_tb <= 0 || n_work <= 0 || n_work > ((int64_t)1 << 30)) return hipErrorInvalidValue;
     const int grid = (int)((n_work + 7) / 8) * 8;
-    const int64_t k_stride = (int64_t)n_tb_cap * N * (2 * kRowBytes);
+    const int64_t k_stride = channel_stride(n_tb_cap, N);
     const int64_t B = (int64_t)N * (N + 1) / 2;
     hipLaunchKernelGGL(xengine_kernel<PREC>, dim3(grid), dim3(kXThreads), 0, stream,
                        static_cast<const uint8_t *>(spec), N, n_tiles, (int)n_work, n_tb, tv, k_stride,
