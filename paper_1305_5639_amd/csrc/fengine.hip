@@ -2,20 +2,26 @@
 // epilogue that writes the X-engine's time-blocked planar spectra layout.
 //
 // One workgroup of 256 threads transforms T = 8192 / C consecutive spectra of
-// one input (64 KB of complex64 voltages, read as one contiguous coalesced
-// run).  The FFT is a Stockham autosort transform: a first pass of radix 2, 4
-// or 8 read straight from global memory into registers, then radix-8 passes
-// through LDS; the last pass leaves channel k = j + r*C/8 of each spectrum in
-// registers.  There the value is scaled by inv_s[k], rounded to the spectra
-// element type, and staged in LDS as [plane][channel][spectrum], which turns
-// the channel-major FFT output into runs of consecutive spectra per
-// (channel, input, plane) row of the X-engine layout.
+// one input (64 KB of complex64 voltages, one contiguous coalesced run); every
+// thread holds 32 complex values.  The FFT is a Stockham autosort transform
+// with radices up to 32 done in registers: one pass for C <= 32, two for
+// C <= 1024 (one LDS round trip), three above.  The first pass reads straight
+// from global memory; the others read and write LDS rows whose index is padded
+// (one slot every 16 or 32, plus a few per row, chosen per C) so that the
+// strided Stockham stores and loads are free of bank conflicts.  The last pass
+// maps neighbouring lanes to neighbouring spectra of one channel; its values
+// are scaled by inv_s[k], rounded to the spectra element type and staged in
+// LDS as [plane][channel][spectrum], which turns the channel-major FFT output
+// into runs of consecutive spectra per (channel, input, plane) row of the
+// X-engine layout.
 //
-// Twiddles are float32 values of exp(-j 2 pi m / C) computed in float64 on the
-// host.  Workgroups are mapped XCD-major (each XCD takes a contiguous range of
-// work items), so the workgroups that fill the same 128-byte spectra rows run
-// on one XCD at about the same time and their partial-row stores merge in
-// that XCD's L2.
+// Twiddles between passes are float32 values of exp(-j 2 pi m / C) computed
+// in float64 on the host: log2(R) table reads per butterfly, the other powers
+// as products (at most log2(R) - 1 deep).  The twiddles inside a radix-R
+// butterfly are constants.  Workgroups are numbered XCD-major (each XCD takes
+// a contiguous range of work items), so the workgroups that fill the same
+// 128-byte spectra rows run on one XCD at about the same time and their
+// partial-row stores merge in that XCD's L2.
 #include "corr_internal.h"
 
 namespace corr {
@@ -30,61 +36,79 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-// multiply by -j
-__device__ __forceinline__ float2 mul_mj(float2 a) { return make_float2(a.y, -a.x); }
 
-template <int R> __device__ __forceinline__ void dft(float2 *v);
+// exp(-j 2 pi k / 32), k = 0..15.
+__constant__ const float kW32[16][2] = {
+    {1.000000000f, -0.000000000f},  {0.980785280f, -0.195090322f},  {0.923879533f, -0.382683432f},
+    {0.831469612f, -0.555570233f},  {0.707106781f, -0.707106781f},  {0.555570233f, -0.831469612f},
+    {0.382683432f, -0.923879533f},  {0.195090322f, -0.980785280f},  {0.000000000f, -1.000000000f},
+    {-0.195090322f, -0.980785280f}, {-0.382683432f, -0.923879533f}, {-0.555570233f, -0.831469612f},
+    {-0.707106781f, -0.707106781f}, {-0.831469612f, -0.555570233f}, {-0.923879533f, -0.382683432f},
+    {-0.980785280f, -0.195090322f},
+};
 
-template <> __device__ __forceinline__ void dft<2>(float2 *v) {
-    float2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
+// x * exp(-j 2 pi k / R) for a compile-time k / R, with the trivial angles exact.
+template <int R, int K>
+__device__ __forceinline__ float2 rot(float2 x) {
+    constexpr int k32 = K * (32 / R);                  // angle in units of 2 pi / 32, < 16
+    if constexpr (k32 == 0) return x;
+    else if constexpr (k32 == 8) return make_float2(x.y, -x.x);      // -j
+    else return cmul(x, make_float2(kW32[k32][0], kW32[k32][1]));
 }
 
-// Forward 4-point DFT, twiddle e^{-j pi/2} = -j.
-template <> __device__ __forceinline__ void dft<4>(float2 *v) {
-    float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-    float2 s13 = cadd(v[1], v[3]), d13 = mul_mj(csub(v[1], v[3]));
-    v[0] = cadd(s02, s13);
-    v[2] = csub(s02, s13);
-    v[1] = cadd(d02, d13);
-    v[3] = csub(d02, d13);
-}
+// Forward R-point DFT in registers (R a power of two, <= 32), decimation in
+// time: two R/2-point DFTs of the even and odd samples joined by W_R^k.
+template <int R> struct Dft {
+    template <int K = 0>
+    static __device__ __forceinline__ void join(float2 *v, const float2 *e, const float2 *o) {
+        if constexpr (K < R / 2) {
+            const float2 t = rot<R, K>(o[K]);
+            v[K] = cadd(e[K], t);
+            v[K + R / 2] = csub(e[K], t);
+            join<K + 1>(v, e, o);
+        }
+    }
+    static __device__ __forceinline__ void run(float2 *v) {
+        if constexpr (R == 1) {
+            return;
+        } else if constexpr (R == 2) {
+            const float2 a = v[0], b = v[1];
+            v[0] = cadd(a, b);
+            v[1] = csub(a, b);
+        } else {
+            float2 e[R / 2], o[R / 2];
+#pragma unroll
+            for (int i = 0; i < R / 2; ++i) {
+                e[i] = v[2 * i];
+                o[i] = v[2 * i + 1];
+            }
+            Dft<R / 2>::run(e);
+            Dft<R / 2>::run(o);
+            join(v, e, o);
+        }
+    }
+};
 
-// Forward 8-point DFT as two 4-point DFTs of the even and odd samples joined
-// with w8^k = e^{-j pi k / 4}.
-template <> __device__ __forceinline__ void dft<8>(float2 *v) {
-    float2 e[4] = {v[0], v[2], v[4], v[6]};
-    float2 o[4] = {v[1], v[3], v[5], v[7]};
-    dft<4>(e);
-    dft<4>(o);
-    const float c = 0.70710678118654752440f;
-    float2 o1 = make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
-    float2 o2 = mul_mj(o[2]);
-    float2 o3 = make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
-    v[0] = cadd(e[0], o[0]);
-    v[4] = csub(e[0], o[0]);
-    v[1] = cadd(e[1], o1);
-    v[5] = csub(e[1], o1);
-    v[2] = cadd(e[2], o2);
-    v[6] = csub(e[2], o2);
-    v[3] = cadd(e[3], o3);
-    v[7] = csub(e[3], o3);
-}
+// Radices of the passes (product C, each <= 32) and the LDS row padding:
+// element i of a row is stored at i + (i >> SH), rows are C + (C >> SH) + EX
+// apart.  The paddings come from a bank-mapping simulation of every pass.
+template <int C> struct Plan;
+template <> struct Plan<16> { static constexpr int NP = 1, R0 = 16, R1 = 1, R2 = 1, SH = 5, EX = 0; };
+template <> struct Plan<32> { static constexpr int NP = 1, R0 = 32, R1 = 1, R2 = 1, SH = 5, EX = 0; };
+template <> struct Plan<64> { static constexpr int NP = 2, R0 = 8, R1 = 8, R2 = 1, SH = 5, EX = 1; };
+template <> struct Plan<128> { static constexpr int NP = 2, R0 = 8, R1 = 16, R2 = 1, SH = 4, EX = 1; };
+template <> struct Plan<256> { static constexpr int NP = 2, R0 = 16, R1 = 16, R2 = 1, SH = 4, EX = 1; };
+template <> struct Plan<512> { static constexpr int NP = 2, R0 = 16, R1 = 32, R2 = 1, SH = 4, EX = 1; };
+template <> struct Plan<1024> { static constexpr int NP = 2, R0 = 32, R1 = 32, R2 = 1, SH = 5, EX = 2; };
+template <> struct Plan<2048> { static constexpr int NP = 3, R0 = 8, R1 = 16, R2 = 16, SH = 4, EX = 4; };
+template <> struct Plan<4096> { static constexpr int NP = 3, R0 = 16, R1 = 16, R2 = 16, SH = 4, EX = 8; };
+template <> struct Plan<8192> { static constexpr int NP = 3, R0 = 8, R1 = 32, R2 = 32, SH = 5, EX = 0; };
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
-// Radix of the first pass so that the remaining passes are all radix 8.
-template <int C> constexpr int first_radix() {
-    return (ilog2(C) % 3 == 0) ? 8 : (ilog2(C) % 3 == 1 ? 2 : 4);
-}
 
-// One Stockham pass of radix R after NS points have been combined:
-// butterfly (t, j) reads x[t][j + r C/R], twiddles element r by
-// W^(r (j mod NS) C/(NS R)), and writes x[t][(j/NS) NS R + j mod NS + r NS].
-// Spectrum t occupies LDS row t with a padded stride CP.  Butterfly b of a
-// thread maps to (t, j) = (b / (C/R), b % (C/R)), except in the last pass
-// (REMAP), where (t, j) = (b % T, b / T) so that neighbouring lanes hold
-// neighbouring spectra of one channel for the transposing epilogue.
+// Butterfly b of a pass of radix R maps to (spectrum t, index j): (b / (C/R),
+// b % (C/R)), or in the last pass (b % T, b / T) so that neighbouring lanes
+// hold neighbouring spectra of one channel.
 template <int C, int T, int R, bool REMAP>
 __device__ __forceinline__ void bfly_index(int b, int &t, int &j) {
     if constexpr (REMAP) {
@@ -96,71 +120,81 @@ __device__ __forceinline__ void bfly_index(int b, int &t, int &j) {
     }
 }
 
-template <int C, int T, int R, int NS, bool REMAP>
-__device__ __forceinline__ void pass_compute(float2 *v, const float2 *__restrict__ tw, int tid) {
+// One Stockham pass of radix R after NS points have been combined: butterfly
+// (t, j) takes x[t][j + r C/R], multiplies element r by W_C^(r (j mod NS) C/(NS R)),
+// does an R-point DFT and (unless LAST) writes x[t][(j/NS) NS R + j mod NS + r NS].
+template <int C, int T, int R, int NS, bool FIRST, bool LAST>
+__device__ __forceinline__ void fft_pass(float2 *v, float2 *lds, const float2 *__restrict__ src, int a0,
+                                         int n_spectra, const float2 *__restrict__ tw, int tid) {
+    using P = Plan<C>;
+    constexpr int CP = C + (C >> P::SH) + P::EX;
     constexpr int Q = kPerThread / R;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if constexpr (NS > 1) {
-            int t, j;
-            bfly_index<C, T, R, REMAP>(tid + kThreads * q, t, j);
-            const int m = (j % NS) * (C / (NS * R));
-            if constexpr (R == 8) {
-                // three table reads, the other powers by products (depth <= 2)
-                const float2 w1 = tw[m], w2 = tw[2 * m], w4 = tw[4 * m];
-                const float2 w3 = cmul(w1, w2);
-                v[q * R + 1] = cmul(v[q * R + 1], w1);
-                v[q * R + 2] = cmul(v[q * R + 2], w2);
-                v[q * R + 3] = cmul(v[q * R + 3], w3);
-                v[q * R + 4] = cmul(v[q * R + 4], w4);
-                v[q * R + 5] = cmul(v[q * R + 5], cmul(w1, w4));
-                v[q * R + 6] = cmul(v[q * R + 6], cmul(w2, w4));
-                v[q * R + 7] = cmul(v[q * R + 7], cmul(w3, w4));
-            } else {
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], tw[r * m]);
-            }
-        }
-        dft<R>(v + q * R);
-    }
-}
-
-template <int C, int T, int CP, int R, bool REMAP>
-__device__ __forceinline__ void pass_load_lds(float2 *v, const float2 *lds, int tid) {
-    constexpr int Q = kPerThread / R;
+    constexpr int CR = C / R;
+    constexpr bool REMAP = LAST && !FIRST;
+    if constexpr (!FIRST) __syncthreads();             // the previous pass's stores are visible
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int t, j;
         bfly_index<C, T, R, REMAP>(tid + kThreads * q, t, j);
+        float2 *x = v + q * R;
+        if constexpr (FIRST) {
+            const bool ok = (a0 + t) < n_spectra;
+            const float2 *row = src + (int64_t)(a0 + t) * C + j;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q * R + r] = lds[t * CP + j + r * (C / R)];
+            for (int r = 0; r < R; ++r) x[r] = ok ? row[r * CR] : make_float2(0.f, 0.f);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = j + r * CR;
+                x[r] = lds[t * CP + i + (i >> P::SH)];
+            }
+        }
+        if constexpr (NS > 1) {
+            constexpr int LR = ilog2(R);
+            const int m = (j % NS) * (C / (NS * R));
+            float2 wp[LR];                             // W^(m 2^i)
+#pragma unroll
+            for (int i = 0; i < LR; ++i) wp[i] = tw[m << i];
+            float2 w[R];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const int hb = 31 - __builtin_clz(r);
+                w[r] = (r == (1 << hb)) ? wp[hb] : cmul(w[r - (1 << hb)], wp[hb]);
+                x[r] = cmul(x[r], w[r]);
+            }
+        }
+        Dft<R>::run(x);
     }
-}
-
-template <int C, int T, int CP, int R, int NS>
-__device__ __forceinline__ void pass_store_lds(const float2 *v, float2 *lds, int tid) {
-    constexpr int Q = kPerThread / R;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        int t, j;
-        bfly_index<C, T, R, false>(tid + kThreads * q, t, j);
-        const int base = t * CP + (j / NS) * NS * R + (j % NS);
-#pragma unroll
-        for (int r = 0; r < R; ++r) lds[base + r * NS] = v[q * R + r];
-    }
-}
-
-// Passes after the first: NS points already combined, radix 8 from here on.
-template <int C, int T, int CP, int NS>
-__device__ __forceinline__ void later_passes(float2 *v, float2 *lds, const float2 *__restrict__ tw, int tid) {
-    constexpr bool LAST = NS * 8 == C;
-    __syncthreads();
-    pass_load_lds<C, T, CP, 8, LAST>(v, lds, tid);
-    pass_compute<C, T, 8, NS, LAST>(v, tw, tid);
     if constexpr (!LAST) {
-        __syncthreads();
-        pass_store_lds<C, T, CP, 8, NS>(v, lds, tid);
-        later_passes<C, T, CP, NS * 8>(v, lds, tw, tid);
+        if constexpr (!FIRST) __syncthreads();         // every thread has read this pass's inputs
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            int t, j;
+            bfly_index<C, T, R, false>(tid + kThreads * q, t, j);
+            const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = base + r * NS;
+                lds[t * CP + i + (i >> P::SH)] = v[q * R + r];
+            }
+        }
+    }
+}
+
+// The passes of Plan<C>; v ends with the last pass's outputs in registers.
+template <int C, int T>
+__device__ __forceinline__ void fft(float2 *v, float2 *lds, const float2 *__restrict__ src, int a0, int n_spectra,
+                                    const float2 *__restrict__ tw, int tid) {
+    using P = Plan<C>;
+    if constexpr (P::NP == 1) {
+        fft_pass<C, T, P::R0, 1, true, true>(v, lds, src, a0, n_spectra, tw, tid);
+    } else if constexpr (P::NP == 2) {
+        fft_pass<C, T, P::R0, 1, true, false>(v, lds, src, a0, n_spectra, tw, tid);
+        fft_pass<C, T, P::R1, P::R0, false, true>(v, lds, src, a0, n_spectra, tw, tid);
+    } else {
+        fft_pass<C, T, P::R0, 1, true, false>(v, lds, src, a0, n_spectra, tw, tid);
+        fft_pass<C, T, P::R1, P::R0, false, false>(v, lds, src, a0, n_spectra, tw, tid);
+        fft_pass<C, T, P::R2, P::R0 * P::R1, false, true>(v, lds, src, a0, n_spectra, tw, tid);
     }
 }
 
@@ -219,14 +253,14 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(
     const float2 *__restrict__ tw, uint8_t *__restrict__ spec, int n_tb_cap) {
     using E = typename Elem<PREC>::T;
     constexpr int T = kTC / C;                         // spectra per workgroup
-    constexpr int PAD = T >= 64 ? 1 : 64 / T;          // LDS row padding (float2)
-    constexpr int CP = C + PAD;                        // LDS row stride (float2)
+    using P = Plan<C>;
+    static_assert(P::R0 * P::R1 * P::R2 == C, "radix plan must multiply to C");
+    constexpr int RL = P::NP == 1 ? P::R0 : (P::NP == 2 ? P::R1 : P::R2);   // last radix
+    constexpr int CP = C + (C >> P::SH) + P::EX;       // LDS row stride (float2)
     constexpr int ES = (int)sizeof(E);
     constexpr int TB = kRowBytes / ES;                 // spectra per time block
     constexpr int S = T * ES;                          // bytes of one staged row
     constexpr int CH = S < 16 ? S : 16;                // store chunk
-    constexpr int R0 = first_radix<C>();
-    static_assert(R0 < C, "at least two passes");
     static_assert(2 * C * S <= T * CP * 8, "staging must fit the FFT buffer");
 
     __shared__ __attribute__((aligned(16))) float2 lds[T * CP];
@@ -240,37 +274,22 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(
     const int a0 = (w % groups_per_input) * T;
 
     float2 v[kPerThread];
-    {
-        constexpr int Q = kPerThread / R0;
-        constexpr int CR = C / R0;
-        const float2 *src = volts + (int64_t)p * ld;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int b = tid + kThreads * q;
-            const int t = b / CR, j = b % CR;
-            const bool ok = (a0 + t) < n_spectra;
-            const float2 *row = src + (int64_t)(a0 + t) * C + j;
-#pragma unroll
-            for (int r = 0; r < R0; ++r) v[q * R0 + r] = ok ? row[r * CR] : make_float2(0.f, 0.f);
-        }
-        pass_compute<C, T, R0, 1, false>(v, tw, tid);
-        pass_store_lds<C, T, CP, R0, 1>(v, lds, tid);
-        later_passes<C, T, CP, R0>(v, lds, tw, tid);
-    }
-    // v now holds, for last-pass butterfly b = tid + 256 q, channel
-    // k = j + r C/8 of spectrum t, with t = b % T and j = b / T.
-    constexpr int CR = C / 8;
+    fft<C, T>(v, lds, volts + (int64_t)p * ld, a0, n_spectra, tw, tid);
+
+    // v[q RL + r] holds channel k = j + r C/RL of spectrum t for last-pass
+    // butterfly b = tid + 256 q, (t, j) = (b % T, b / T).
+    constexpr int CR = C / RL;
     __syncthreads();                                   // every thread is done reading lds
     uint8_t *stage = reinterpret_cast<uint8_t *>(lds); // [plane][k][T] elements
 #pragma unroll
-    for (int q = 0; q < kPerThread / 8; ++q) {
+    for (int q = 0; q < kPerThread / RL; ++q) {
         const int b = tid + kThreads * q;
         const int t = b % T, j = b / T;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < RL; ++r) {
             const int k = j + r * CR;
             const float s = inv_scale ? inv_scale[k] : 1.0f;
-            const float2 y = v[q * 8 + r];
+            const float2 y = v[q * RL + r];
             *reinterpret_cast<E *>(stage + (0 * C + k) * S + t * ES) = Elem<PREC>::conv(y.x * s);
             *reinterpret_cast<E *>(stage + (1 * C + k) * S + t * ES) = Elem<PREC>::conv(y.y * s);
         }

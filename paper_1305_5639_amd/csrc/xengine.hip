@@ -29,6 +29,8 @@
 // The epilogue scales by s_k^2 (float forms) and adds into the persistent
 // lower-triangle accumulators (or writes them on the first call of an
 // integration); autos get an exactly zero imaginary part, as Eq. 2 gives.
+#include <type_traits>
+
 #include "corr_internal.h"
 
 namespace corr {
@@ -39,6 +41,7 @@ typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXThreads = 256;
 constexpr int kTile = 128;
@@ -47,31 +50,32 @@ constexpr int kOpBytes = kTile * kRowStride;
 constexpr int kStageBytes = 2 * kOpBytes;
 
 // Per-precision fragment type and MFMA step.  A lane owns 32 bytes of each
-// (row, plane) per time block; KS MFMA K steps consume them, FB bytes each.
+// (row, plane) per time block, read as KS fragments of FB bytes; each
+// fragment feeds NSUB MFMAs (sub-element e of the fragment).
 template <int PREC> struct XT;
 
 template <> struct XT<P_FP32> {
     using Acc = f32x16;
-    using Frag = float;
-    static constexpr int KS = 8, FB = 4;
-    static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const float *>(p); }
+    using Frag = f32x4;   // 4 spectra; 16-byte LDS reads are bank-conflict free
+    static constexpr int KS = 2, FB = 16, NSUB = 4;
+    static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const f32x4 *>(p); }
     static __device__ __forceinline__ Frag neg(Frag b) { return -b; }
-    static __device__ __forceinline__ void mfma(Acc &c, Frag a, Frag b) {
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int e) {
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], c, 0, 0, 0);
     }
 };
 
 template <> struct XT<P_FP16> {
     using Acc = f32x16;
     using Frag = i32x4;
-    static constexpr int KS = 2, FB = 16;
+    static constexpr int KS = 2, FB = 16, NSUB = 1;
     static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const i32x4 *>(p); }
     static __device__ __forceinline__ Frag neg(Frag b) {
         return Frag{b[0] ^ (int)0x80008000u, b[1] ^ (int)0x80008000u, b[2] ^ (int)0x80008000u,
                     b[3] ^ (int)0x80008000u};
     }
     static __device__ __forceinline__ f16x8 h8(Frag x) { return __builtin_bit_cast(f16x8, x); }
-    static __device__ __forceinline__ void mfma(Acc &c, Frag a, Frag b) {
+    static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int) {
         c = __builtin_amdgcn_mfma_f32_32x32x16_f16(h8(a), h8(b), c, 0, 0, 0);
     }
 };
@@ -79,7 +83,7 @@ template <> struct XT<P_FP16> {
 template <> struct XT<P_INT8> {
     using Acc = i32x16;
     using Frag = i32x4;
-    static constexpr int KS = 2, FB = 16;
+    static constexpr int KS = 2, FB = 16, NSUB = 1;
     static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const i32x4 *>(p); }
     // Byte-wise 0 - b without borrows between bytes.
     static __device__ __forceinline__ int neg4(int v) {
@@ -87,7 +91,7 @@ template <> struct XT<P_INT8> {
         return (int)((0x80808080u - (x & 0x7f7f7f7fu)) ^ (~x & 0x80808080u));
     }
     static __device__ __forceinline__ Frag neg(Frag b) { return Frag{neg4(b[0]), neg4(b[1]), neg4(b[2]), neg4(b[3])}; }
-    static __device__ __forceinline__ void mfma(Acc &c, Frag a, Frag b) {
+    static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int) {
         c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
     }
 };
@@ -95,7 +99,7 @@ template <> struct XT<P_INT8> {
 template <> struct XT<P_FP8> {
     using Acc = f32x16;
     using Frag = i32x8;
-    static constexpr int KS = 1, FB = 32;
+    static constexpr int KS = 1, FB = 32, NSUB = 1;
     static __device__ __forceinline__ Frag load(const uint8_t *p) {
         const i32x4 a = *reinterpret_cast<const i32x4 *>(p);
         const i32x4 b = *reinterpret_cast<const i32x4 *>(p + 16);
@@ -108,85 +112,113 @@ template <> struct XT<P_FP8> {
         return r;
     }
     // Format code 0 = FP8 E4M3 for both operands; E8M0 scale 127 = 2^0.
-    static __device__ __forceinline__ void mfma(Acc &c, Frag a, Frag b) {
+    static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int) {
         c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
     }
 };
 
+// One time block of a wave's 64x64 quarter: KS fragment reads per (row or
+// column half, plane), NSUB MFMAs per fragment, four real products per 32x32
+// block (Re += Ar Br + Ai Bi, Im += Ar Bi + Ai (-Br)), issued across both
+// column halves so dependent MFMAs are apart.  SKIP_UPPER: a diagonal wave
+// leaves out its upper 32x32 block (rows 0-31, columns 32-63).
+template <int PREC, bool SKIP_UPPER, typename Acc>
+__device__ __forceinline__ void wave_block(Acc (&re)[2][2], Acc (&im)[2][2], const uint8_t *pa,
+                                           const uint8_t *pb) {
+    using X = XT<PREC>;
+#pragma unroll
+    for (int s = 0; s < X::KS; ++s) {
+        typename X::Frag b[2][2], nb[2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            b[g][0] = X::load(pb + g * 32 * kRowStride + s * X::FB);
+            b[g][1] = X::load(pb + g * 32 * kRowStride + kRowBytes + s * X::FB);
+            nb[g] = X::neg(b[g][0]);
+        }
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const typename X::Frag ar = X::load(pa + f * 32 * kRowStride + s * X::FB);
+            const typename X::Frag ai = X::load(pa + f * 32 * kRowStride + kRowBytes + s * X::FB);
+            const bool up = SKIP_UPPER && f == 0;
+#pragma unroll
+            for (int e = 0; e < X::NSUB; ++e) {
+                X::mfma(re[f][0], ar, b[0][0], e);                  // + xr_i xr_j
+                if (!up) X::mfma(re[f][1], ar, b[1][0], e);
+                X::mfma(im[f][0], ar, b[0][1], e);                  // + xr_i xi_j
+                if (!up) X::mfma(im[f][1], ar, b[1][1], e);
+                X::mfma(re[f][0], ai, b[0][1], e);                  // + xi_i xi_j
+                if (!up) X::mfma(re[f][1], ai, b[1][1], e);
+                X::mfma(im[f][0], ai, nb[0], e);                    // - xi_i xr_j
+                if (!up) X::mfma(im[f][1], ai, nb[1], e);
+            }
+        }
+    }
+}
+
+// The whole K loop and epilogue of one 128x128 block of channel k, rows
+// I0.., columns J0...  Both operand slabs are always staged (a diagonal block
+// stages the same rows twice) so the staging code has no branches between
+// its global loads.
 template <int PREC>
-__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void xengine_kernel(
-    const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
-    int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, int64_t B,
-    int first_call) {
+__device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ base_k, int N, int n_tb, int tv,
+                                     int I0, int J0, int k, const float *__restrict__ scale2,
+                                     void *__restrict__ acc_out, int64_t B, int first_call) {
     using Acc = typename XT<PREC>::Acc;
     constexpr int ES = PREC == P_FP32 ? 4 : (PREC == P_FP16 ? 2 : 1);
     constexpr int TB = kRowBytes / ES;
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * kStageBytes];
-
+    constexpr int NOP = 2;                              // operand slabs per stage
+    const bool DIAG = I0 == J0;
     const int tid = threadIdx.x;
-    const int per = (n_work + 7) / 8;
-    const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (w >= n_work) return;
-    const int k = w / n_tiles;
-    const int t = w % n_tiles;
-    int bi = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-    while (bi * (bi + 1) / 2 > t) --bi;
-    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-    const int bj = t - bi * (bi + 1) / 2;
-    const bool diag = bi == bj;
-    const int I0 = bi * kTile, J0 = bj * kTile;
-
     const int wave = tid >> 6, lane = tid & 63;
     const int wi = wave >> 1, wj = wave & 1;
     const int m = lane & 31, h = lane >> 5;
-    const bool active = !(diag && wj > wi);
-    const bool dwave = diag && wi == wj;     // diagonal wave: skip its upper 32x32 block
+    const bool active = !(DIAG && wj > wi);
+    const bool dwave = DIAG && wi == wj;     // diagonal wave: skip its upper 32x32 block
 
-    const uint8_t *base_k = spec + (int64_t)k * k_stride;
-
-    uint4 st[8];
+    // Global -> register staging of one time block.  The loads are issued
+    // unconditionally (rows past N read row N-1) and nothing inspects the
+    // registers until store_stage, which runs after the block's MFMAs, so the
+    // loads stay in flight during the compute.  store_stage zeroes rows past N
+    // and, in the last time block, spectra past the valid count.
+    uint4 st[4 * NOP];
     auto load_stage = [&](int tb) {
         const uint8_t *blk = base_k + (int64_t)tb * N * (2 * kRowBytes);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = tid + kXThreads * u;
-            const int row = c >> 3, col = c & 7;
-            const int pI = I0 + row;
-            st[u] = pI < N ? *reinterpret_cast<const uint4 *>(blk + (int64_t)pI * (2 * kRowBytes) + col * 16)
-                           : make_uint4(0, 0, 0, 0);
-            if (!diag) {
-                const int pJ = J0 + row;
-                st[4 + u] = pJ < N ? *reinterpret_cast<const uint4 *>(blk + (int64_t)pJ * (2 * kRowBytes) + col * 16)
-                                   : make_uint4(0, 0, 0, 0);
+        for (int o = 0; o < NOP; ++o)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = tid + kXThreads * u;
+                const int row = c >> 3, col = c & 7;
+                const int pr = min((o ? J0 : I0) + row, N - 1);
+                st[4 * o + u] = *reinterpret_cast<const uint4 *>(blk + (int64_t)pr * (2 * kRowBytes) + col * 16);
             }
-        }
-        if (tb == n_tb - 1 && tv < TB) {
-            // zero the spectra past the valid count in the last time block
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int c = tid + kXThreads * (u & 3);
-                const int off = ((c & 7) & 3) * 16;
-                uint32_t *wd = reinterpret_cast<uint32_t *>(&st[u]);
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    uint32_t msk = 0;
-#pragma unroll
-                    for (int bb = 0; bb < 4; ++bb)
-                        if ((off + 4 * d + bb) / ES < tv) msk |= 0xffu << (8 * bb);
-                    wd[d] &= msk;
-                }
-            }
-        }
     };
-    auto store_stage = [&](int buf) {
-        uint8_t *s = smem + buf * kStageBytes;
+    auto store_stage = [&](int buf, int tb) {
+        uint8_t *sm = smem + buf * kStageBytes;
+        const bool tail = tb == n_tb - 1 && tv < TB;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = tid + kXThreads * u;
-            const int row = c >> 3, col = c & 7;
-            *reinterpret_cast<uint4 *>(s + row * kRowStride + col * 16) = st[u];
-            if (!diag) *reinterpret_cast<uint4 *>(s + kOpBytes + row * kRowStride + col * 16) = st[4 + u];
-        }
+        for (int o = 0; o < NOP; ++o)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = tid + kXThreads * u;
+                const int row = c >> 3, col = c & 7;
+                uint4 v = st[4 * o + u];
+                if ((o ? J0 : I0) + row >= N) v = make_uint4(0, 0, 0, 0);
+                if (tail) {
+                    // zero the spectra past the valid count in the last time block
+                    const int off = (col & 3) * 16;
+                    uint32_t *wd = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        uint32_t msk = 0;
+#pragma unroll
+                        for (int bb = 0; bb < 4; ++bb)
+                            if ((off + 4 * d + bb) / ES < tv) msk |= 0xffu << (8 * bb);
+                        wd[d] &= msk;
+                    }
+                }
+                *reinterpret_cast<uint4 *>(sm + o * kOpBytes + row * kRowStride + col * 16) = v;
+            }
     };
 
     Acc re[2][2], im[2][2];
@@ -202,52 +234,32 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2, 2)
         }
 
     load_stage(0);
-    store_stage(0);
+    store_stage(0, 0);
     __syncthreads();
     for (int tb = 0; tb < n_tb; ++tb) {
         const bool more = tb + 1 < n_tb;
         if (more) load_stage(tb + 1);
         if (active) {
-            using X = XT<PREC>;
             const uint8_t *sI = smem + (tb & 1) * kStageBytes;
-            const uint8_t *sJ = diag ? sI : sI + kOpBytes;
+            const uint8_t *sJ = sI + kOpBytes;
             const uint8_t *pa = sI + (wi * 64 + m) * kRowStride + h * 32;
             const uint8_t *pb = sJ + (wj * 64 + m) * kRowStride + h * 32;
-#pragma unroll
-            for (int s = 0; s < X::KS; ++s) {
-                // B fragments (columns j) for both 32-column halves, then each
-                // 32-row half of A in turn; the four real products of a block
-                // are issued across both halves so dependent MFMAs are apart.
-                typename X::Frag b[2][2], nb[2];
-#pragma unroll
-                for (int g = 0; g < 2; ++g) {
-                    b[g][0] = X::load(pb + g * 32 * kRowStride + s * X::FB);
-                    b[g][1] = X::load(pb + g * 32 * kRowStride + kRowBytes + s * X::FB);
-                    nb[g] = X::neg(b[g][0]);
-                }
-#pragma unroll
-                for (int f = 0; f < 2; ++f) {
-                    const typename X::Frag ar = X::load(pa + f * 32 * kRowStride + s * X::FB);
-                    const typename X::Frag ai = X::load(pa + f * 32 * kRowStride + kRowBytes + s * X::FB);
-                    // a diagonal wave skips its upper block (f = 0, g = 1)
-                    const bool up = dwave && f == 0;
-                    X::mfma(re[f][0], ar, b[0][0]);                 // + xr_i xr_j
-                    if (!up) X::mfma(re[f][1], ar, b[1][0]);
-                    X::mfma(im[f][0], ar, b[0][1]);                 // + xr_i xi_j
-                    if (!up) X::mfma(im[f][1], ar, b[1][1]);
-                    X::mfma(re[f][0], ai, b[0][1]);                 // + xi_i xi_j
-                    if (!up) X::mfma(re[f][1], ai, b[1][1]);
-                    X::mfma(im[f][0], ai, nb[0]);                   // - xi_i xr_j
-                    if (!up) X::mfma(im[f][1], ai, nb[1]);
-                }
-            }
+            // one uniform branch per block keeps the MFMA stream branch-free
+            if (dwave)
+                wave_block<PREC, true>(re, im, pa, pb);
+            else
+                wave_block<PREC, false>(re, im, pa, pb);
         }
-        if (more) store_stage((tb + 1) & 1);
+        if (more) store_stage((tb + 1) & 1, tb + 1);
         __syncthreads();
     }
     if (!active) return;
 
-    // Epilogue: 32x32 block element (row 8(r/4) + 4h + r%4, column m).
+    // Epilogue: element r of a 32x32 block is (row 8(r/4) + 4h + r%4, column m).
+    // All of a block's accumulator reads are issued before any write; elements
+    // outside the triangle or past N read a valid address and are not written.
+    using T2 = typename std::conditional<PREC == P_INT8, int2, float2>::type;
+    T2 *out = reinterpret_cast<T2 *>(acc_out) + (int64_t)k * B;
     const float s2 = (PREC != P_INT8 && scale2) ? scale2[k] : 1.0f;
 #pragma unroll
     for (int f = 0; f < 2; ++f)
@@ -255,32 +267,55 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2, 2)
         for (int g = 0; g < 2; ++g) {
             if (dwave && f < g) continue;
             const int j = J0 + wj * 64 + g * 32 + m;
+            int64_t idx[16];
+            uint32_t ok = 0;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int i = I0 + wi * 64 + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                if (i >= N || j > i) continue;
-                const int64_t idx = (int64_t)k * B + (int64_t)i * (i + 1) / 2 + j;
+                const bool in = i < N && j <= i;
+                ok |= (uint32_t)in << r;
+                idx[r] = in ? (int64_t)i * (i + 1) / 2 + j : 0;
+            }
+            T2 old[16];
+            if (!first_call) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) old[r] = out[idx[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = I0 + wi * 64 + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                T2 v;
                 if constexpr (PREC == P_INT8) {
-                    int2 v = make_int2(re[f][g][r], i == j ? 0 : im[f][g][r]);
-                    int2 *o = reinterpret_cast<int2 *>(acc_out) + idx;
-                    if (!first_call) {
-                        const int2 old = *o;
-                        v.x += old.x;
-                        v.y += old.y;
-                    }
-                    *o = v;
+                    v = make_int2(re[f][g][r], i == j ? 0 : im[f][g][r]);
                 } else {
-                    float2 v = make_float2(re[f][g][r] * s2, i == j ? 0.0f : im[f][g][r] * s2);
-                    float2 *o = reinterpret_cast<float2 *>(acc_out) + idx;
-                    if (!first_call) {
-                        const float2 old = *o;
-                        v.x += old.x;
-                        v.y += old.y;
-                    }
-                    *o = v;
+                    v = make_float2(re[f][g][r] * s2, i == j ? 0.0f : im[f][g][r] * s2);
                 }
+                if (!first_call) {
+                    v.x += old[r].x;
+                    v.y += old[r].y;
+                }
+                if ((ok >> r) & 1u) out[idx[r]] = v;
             }
         }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void xengine_kernel(
+    const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
+    int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, int64_t B,
+    int first_call) {
+    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * kStageBytes];
+    const int per = (n_work + 7) / 8;
+    const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (w >= n_work) return;
+    const int k = w / n_tiles;
+    const int t = w % n_tiles;
+    int bi = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (bi * (bi + 1) / 2 > t) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const uint8_t *base_k = spec + (int64_t)k * k_stride;
+    tile<PREC>(smem, base_k, N, n_tb, tv, bi * kTile, bj * kTile, k, scale2, acc_out, B, first_call);
 }
 
 template <int PREC>
