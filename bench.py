@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--forms", default="fp16,int8,fp8",
                     help="other precisions to time on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-sub-array batched (persistent, graph-captured) section")
+    ap.add_argument("--batched-steps", type=int, default=8,
+                    help="graph replays per integration in the batched section")
     ap.add_argument("--cpu-channels", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -154,6 +158,82 @@ def cpu_baseline(torch, oracle, synth, w, volts, results, n_chan):
     }, errors
 
 
+def run_batched(torch, corr, synth, steps_per_integration, reps=3):
+    """64 uneven sub-arrays, FP16 in / FP32 accumulate.  Each sub-array's
+    integration A_s is processed in `steps_per_integration` time blocks of
+    ceil(A_s / steps) spectra; one time block of every sub-array is one graph
+    replay: 64 F-engine launches, then ONE persistent X-engine launch.
+    Reports the X-engine as one batched launch vs 64 per-array launches (same
+    tuned block sizes), and the graph-replayed F + X step."""
+    prec = "fp16"
+    ws = synth.batched_workloads()
+    ns = [-(-w.n_integrate // steps_per_integration) for w in ws]
+    shapes = [(w.n_stations, w.n_pols, w.n_channels, n) for w, n in zip(ws, ns)]
+    cm_step = sum(w.n_products * w.n_channels * n for w, n in zip(ws, ns))
+    stream = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(stream):
+        volts, invs = [], []
+        for w, n in zip(ws, ns):
+            volts.append(synth.voltages(w, n_spectra=n, device="cuda"))
+            invs.append(torch.from_numpy(synth.inv_scale(w, prec)).to("cuda"))
+        b = corr.Batch(shapes, prec, stream=stream)
+        t0 = time.perf_counter()
+        for i, sub in enumerate(b.subs):
+            sub.fengine(volts[i], ns[i], invs[i])
+        tiles = [sub.autotune(n) for sub, n in zip(b.subs, ns)]
+        tune_s = time.perf_counter() - t0
+        b.xengine(ns)                                          # warm-up; fixes the work list
+        stream.synchronize()
+
+        def timed(fn, k):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(k):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / k
+
+        def per_array():
+            for sub, n in zip(b.subs, ns):
+                sub.xengine(n)
+
+        per_array()
+        t_per = timed(per_array, reps)
+        t_bat = timed(lambda: b.xengine(ns), reps)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for i, sub in enumerate(b.subs):
+                sub.fengine(volts[i], ns[i], invs[i])
+            b.xengine(ns)
+        g.replay()
+        t_step = timed(g.replay, steps_per_integration)
+        stream.synchronize()
+        b.close()
+        del volts, invs
+    torch.cuda.empty_cache()
+    out = {
+        "workload": "batched-64: 64 sub-arrays, stations log-uniform 16..512 x 2 pols, "
+                    "channels 2^(8..12), integration 256..2048 (seed 5), FP16 in / FP32 accumulate",
+        "n_subarrays": len(ws),
+        "cmac_per_step": cm_step,
+        "spectra_per_step": ns,
+        "tiles": tiles,
+        "autotune_s": tune_s,
+        "xengine_batched_ms": t_bat,
+        "xengine_per_array_ms": t_per,
+        "xengine_batched_tcmacs": cm_step / (t_bat * 1e-3) / 1e12,
+        "xengine_per_array_tcmacs": cm_step / (t_per * 1e-3) / 1e12,
+        "batched_speedup_vs_per_array": t_per / t_bat,
+        "graph_step_ms": t_step,
+        "graph_step_tcmacs": cm_step / (t_step * 1e-3) / 1e12,
+        "integration_ms": t_step * steps_per_integration,
+        "steps_per_integration": steps_per_integration,
+    }
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -229,6 +309,13 @@ def main():
                      "step_tcmacs": cmacs / wall_f / 1e12}
         log(f"{fp}: step {wall_f * 1e3:.3f} ms, F {f_ms_f:.3f} ms, X {x_ms_f:.3f} ms")
 
+    batched = None
+    if not args.no_batched:
+        log("batched: 64 uneven sub-arrays")
+        batched = run_batched(torch, corr, synth, args.batched_steps)
+        log(f"batched: X {batched['xengine_batched_ms']:.3f} ms (one launch) vs "
+            f"{batched['xengine_per_array_ms']:.3f} ms (64 launches); graph step {batched['graph_step_ms']:.3f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -262,6 +349,7 @@ def main():
         "fengine_hbm_gbs": (N * A * C * (8 + 2 * ELEM_BYTES[prec])) / (f_ms * 1e-3) / 1e9,
         "roofline": roofline,
         "forms": forms,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

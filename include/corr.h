@@ -191,6 +191,49 @@ CORR_API corr_status corr_copy_spectra(corr_handle h, void *dst, int32_t dst_on_
 /* Number of spectra currently held, and spectra integrated since the last reset. */
 CORR_API corr_status corr_get_counts(corr_handle h, int32_t *n_held, int64_t *n_integrated);
 
+/*
+ * X-engine block size.  The triangle of each channel is covered by square
+ * blocks of `tile` inputs (64 or 128); 0 selects by N (64 for N <= 64, else
+ * 128) unless corr_autotune has chosen.  Larger blocks reuse each operand
+ * more; smaller ones waste less on the diagonal and on ragged N.
+ */
+CORR_API corr_status corr_set_tile(corr_handle h, int32_t tile);
+
+/*
+ * Autotuner: time the X-engine with each block size on the first n_spectra
+ * held spectra (at most 256 channels, into scratch accumulators, so the
+ * integration is untouched), keep the fastest for this handle and write it
+ * to *tile (may be NULL).  Results are cached per (precision, inputs, time
+ * blocks) for the process, and in the text file named by the environment
+ * variable CORR_TUNE_CACHE when it is set.  Synchronises the stream;
+ * CORR_E_STATE while the stream is being captured into a graph.
+ */
+CORR_API corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile);
+
+/*
+ * Batched form: many sub-arrays of uneven size (stations, channels,
+ * integration) correlated by ONE persistent X-engine launch that drains a
+ * work list of (sub-array, channel, block) items, largest first.  All
+ * sub-arrays share one precision and stream.  Each sub-array is an ordinary
+ * handle owned by the batch (corr_batch_get): use corr_fengine,
+ * corr_dump_visibilities and corr_autotune on it as usual; corr_destroy on it
+ * is CORR_E_STATE.  Sub-array accumulators are zeroed at creation and a
+ * dump with reset zeroes them right away (a kernel, not a memset), so a
+ * sequence of corr_fengine / corr_xengine_batched calls can be captured into
+ * a HIP graph once a first corr_xengine_batched call has been made outside
+ * the capture.
+ */
+typedef struct corr_batch *corr_batch_handle;
+
+CORR_API corr_status corr_create_batched(const corr_params *params, int32_t n, void *hip_stream,
+                                         corr_batch_handle *out);
+CORR_API corr_status corr_batch_get(corr_batch_handle b, int32_t i, corr_handle *h);
+
+/* n_spectra: host array [n]; sub-array i correlates its first n_spectra[i]
+ * held spectra (0 = skip).  Same checks as corr_xengine per sub-array. */
+CORR_API corr_status corr_xengine_batched(corr_batch_handle b, const int32_t *n_spectra);
+CORR_API corr_status corr_destroy_batched(corr_batch_handle b);
+
 /* Static text of a status code. */
 CORR_API const char *corr_status_string(corr_status s);
 

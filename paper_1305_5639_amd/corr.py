@@ -42,6 +42,8 @@ ABI_FUNCTIONS = (
     "corr_n_products", "corr_visibility_bytes", "corr_spectra_bytes", "corr_create",
     "corr_destroy", "corr_fengine", "corr_xengine", "corr_dump_visibilities",
     "corr_copy_spectra", "corr_get_counts", "corr_status_string", "corr_last_error",
+    "corr_set_tile", "corr_autotune", "corr_create_batched", "corr_batch_get",
+    "corr_xengine_batched", "corr_destroy_batched",
 )
 
 
@@ -95,8 +97,16 @@ def lib() -> ctypes.CDLL:
         L.corr_status_string.restype = ctypes.c_char_p
         L.corr_last_error.argtypes = [P]
         L.corr_last_error.restype = ctypes.c_char_p
+        L.corr_set_tile.argtypes = [P, i32]
+        L.corr_autotune.argtypes = [P, i32, ctypes.POINTER(i32)]
+        L.corr_create_batched.argtypes = [PP, i32, P, ctypes.POINTER(P)]
+        L.corr_batch_get.argtypes = [P, i32, ctypes.POINTER(P)]
+        L.corr_xengine_batched.argtypes = [P, ctypes.POINTER(i32)]
+        L.corr_destroy_batched.argtypes = [P]
         for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_xengine",
-                  "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts"):
+                  "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts", "corr_set_tile",
+                  "corr_autotune", "corr_create_batched", "corr_batch_get", "corr_xengine_batched",
+                  "corr_destroy_batched"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -208,20 +218,54 @@ def corr_get_counts(h) -> tuple[int, int]:
     return a.value, b.value
 
 
+def corr_set_tile(h, tile: int) -> None:
+    _check(lib().corr_set_tile(h, int(tile)), "corr_set_tile", h)
+
+
+def corr_autotune(h, n_spectra: int) -> int:
+    t = ctypes.c_int32()
+    _check(lib().corr_autotune(h, int(n_spectra), ctypes.byref(t)), "corr_autotune", h)
+    return t.value
+
+
+def corr_create_batched(params_list, stream=None) -> ctypes.c_void_p:
+    arr = (corr_params * len(params_list))(*params_list)
+    b = ctypes.c_void_p()
+    _check(lib().corr_create_batched(arr, len(params_list), _stream(stream), ctypes.byref(b)),
+           "corr_create_batched")
+    return b
+
+
+def corr_batch_get(b, i: int) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().corr_batch_get(b, int(i), ctypes.byref(h)), "corr_batch_get")
+    return h
+
+
+def corr_xengine_batched(b, n_spectra) -> None:
+    arr = (ctypes.c_int32 * len(n_spectra))(*[int(x) for x in n_spectra])
+    _check(lib().corr_xengine_batched(b, arr), "corr_xengine_batched")
+
+
+def corr_destroy_batched(b) -> None:
+    _check(lib().corr_destroy_batched(b), "corr_destroy_batched")
+
+
 # --------------------------------------------------------------------------
-# a small owning wrapper
+# small owning wrappers
 # --------------------------------------------------------------------------
 class Correlator:
     """Owns one handle; methods map one-to-one onto the ABI calls."""
 
     def __init__(self, n_stations, n_pols, n_channels, n_integrate, precision="fp32", layout="lower",
-                 order="chan", device_mem_cap=0, stream=None):
+                 order="chan", device_mem_cap=0, stream=None, _borrowed=None):
         self.params = make_params(n_stations, n_pols, n_channels, n_integrate, precision, layout, order,
                                   device_mem_cap)
         self.n_inputs = n_stations * n_pols
         self.n_channels = n_channels
         self.precision = self.params.precision
-        self.handle = corr_create(self.params, stream)
+        self._owned = _borrowed is None
+        self.handle = corr_create(self.params, stream) if self._owned else _borrowed
 
     def fengine(self, volts, n_spectra, inv_scale=None, ld_samples=None):
         corr_fengine(self.handle, volts, n_spectra, inv_scale, ld_samples)
@@ -255,9 +299,54 @@ class Correlator:
     def counts(self):
         return corr_get_counts(self.handle)
 
+    def set_tile(self, tile):
+        corr_set_tile(self.handle, tile)
+
+    def autotune(self, n_spectra):
+        return corr_autotune(self.handle, n_spectra)
+
+    def close(self):
+        if self.handle and self._owned:
+            corr_destroy(self.handle)
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns a batch of sub-arrays; sub-arrays are borrowed Correlator views."""
+
+    def __init__(self, shapes, precision="fp16", layout="lower", order="chan", stream=None):
+        """shapes: list of (n_stations, n_pols, n_channels, n_integrate)."""
+        plist = [make_params(*sh, precision, layout, order) for sh in shapes]
+        self.handle = corr_create_batched(plist, stream)
+        self.subs = [Correlator(*sh, precision, layout, order, _borrowed=corr_batch_get(self.handle, i))
+                     for i, sh in enumerate(shapes)]
+
+    def __len__(self):
+        return len(self.subs)
+
+    def __getitem__(self, i):
+        return self.subs[i]
+
+    def xengine(self, n_spectra):
+        corr_xengine_batched(self.handle, n_spectra)
+
     def close(self):
         if self.handle:
-            corr_destroy(self.handle)
+            for s in self.subs:
+                s.handle = None
+            corr_destroy_batched(self.handle)
             self.handle = None
 
     def __enter__(self):

@@ -5,11 +5,16 @@
 // invalid-argument, budget and overflow error is decided on the CPU.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "corr.h"
@@ -35,6 +40,20 @@ struct corr_ctx {
     bool held_from_fengine = false;
     int64_t n_integrated = 0;         // spectra integrated since the last reset
     bool acc_zero = true;             // accumulators logically zero
+    int tile = 0;                     // X-engine block size; 0 = by N
+    bool batch_member = false;        // owned by a corr_batch (eager reset)
+    std::string err;
+};
+
+struct corr_batch {
+    std::vector<corr_ctx *> subs;
+    int prec = 0;
+    hipStream_t stream = nullptr;
+    int grid = 0;                     // persistent workgroups (2 per CU)
+    XDesc *d_desc = nullptr;          // device descriptors
+    XDesc *h_desc = nullptr;          // pinned staging of the descriptors
+    std::vector<XDesc> last;          // descriptors last uploaded
+    unsigned int *d_counter = nullptr;
     std::string err;
 };
 
@@ -122,7 +141,45 @@ bool default_dump(const corr_params *p) { return p->layout == CORR_TRI_LOWER && 
 
 bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
+int effective_tile(const corr_ctx *h) { return h->tile ? h->tile : (h->N <= 64 ? 64 : 128); }
+
+const float *x_scale(const corr_ctx *h) {
+    if (h->prec == P_INT8) return nullptr;
+    if (h->held_from_fengine) return h->scale2;
+    return h->prec == P_FP32 ? nullptr : h->scale2_user;
+}
+
+// Autotune cache: (precision, inputs, time blocks) -> block size.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("CORR_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    int p, n, t, tile;
+    while (std::fscanf(f, "%d %d %d %d", &p, &n, &t, &tile) == 4)
+        if (tile == 64 || tile == 128) g_tune[{p, n, t}] = tile;
+    std::fclose(f);
+}
+
+void tune_store_locked(int p, int n, int t, int tile) {
+    g_tune[{p, n, t}] = tile;
+    const char *path = std::getenv("CORR_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %d %d\n", p, n, t, tile);
+    std::fclose(f);
+}
+
 }  // namespace
+
+static void destroy_ctx(corr_ctx *h);
 
 extern "C" {
 
@@ -200,7 +257,7 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
 
     auto cleanup_fail = [&](corr_status st, const std::string &m) {
         g_err = m;
-        corr_destroy(h);
+        destroy_ctx(h);
         return st;
     };
     hipError_t e = hipGetDevice(&h->device);
@@ -246,8 +303,9 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
     return CORR_OK;
 }
 
-corr_status corr_destroy(corr_handle h) {
-    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+}  // extern "C"
+
+static void destroy_ctx(corr_ctx *h) {
     if (h->spec || h->acc) (void)hipStreamSynchronize(h->stream);
     (void)hipFree(h->spec);
     (void)hipFree(h->acc);
@@ -256,6 +314,14 @@ corr_status corr_destroy(corr_handle h) {
     (void)hipFree(h->scale2_user);
     (void)hipFree(h->dump_tmp);
     delete h;
+}
+
+extern "C" {
+
+corr_status corr_destroy(corr_handle h) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (h->batch_member) return fail(h, CORR_E_STATE, "sub-array handles are destroyed with their batch");
+    destroy_ctx(h);
     return CORR_OK;
 }
 
@@ -312,11 +378,11 @@ corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra
             if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
             s2 = h->scale2_user;
         }
-    } else if (h->prec != P_INT8) {
-        s2 = h->held_from_fengine ? h->scale2 : (h->prec == P_FP32 ? nullptr : h->scale2_user);
+    } else {
+        s2 = x_scale(h);
     }
-    e = launch_xengine(h->prec, h->C, h->N, n_spectra, h->n_tb_cap, h->spec, s2, h->acc, h->acc_zero ? 1 : 0,
-                       h->stream);
+    e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->n_tb_cap, h->spec, s2, h->acc,
+                       h->acc_zero ? 1 : 0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
     h->acc_zero = false;
     h->n_integrated += n_spectra;
@@ -362,7 +428,14 @@ corr_status corr_dump_visibilities(corr_handle h, void *dst, int32_t dst_on_devi
         }
     }
     if (reset) {
-        h->acc_zero = true;
+        if (h->batch_member) {
+            // eager: the accumulators are zero in memory, so the batched
+            // X-engine can always accumulate (graph-replay friendly)
+            e = launch_zero(h->acc, (int64_t)(h->acc_bytes / 4), h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "zero launch");
+        } else {
+            h->acc_zero = true;
+        }
         h->n_integrated = 0;
     }
     h->err.clear();
@@ -397,6 +470,227 @@ corr_status corr_get_counts(corr_handle h, int32_t *n_held, int64_t *n_integrate
     if (!n_held || !n_integrated) return fail(h, CORR_E_INVALID_ARG, "output pointer is NULL");
     *n_held = h->n_held;
     *n_integrated = h->n_integrated;
+    return CORR_OK;
+}
+
+
+corr_status corr_set_tile(corr_handle h, int32_t tile) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (tile != 0 && tile != 64 && tile != 128) return fail(h, CORR_E_INVALID_ARG, "tile must be 0, 64 or 128");
+    h->tile = tile;
+    return CORR_OK;
+}
+
+corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile_out) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (n_spectra < 1) return fail(h, CORR_E_INVALID_ARG, "n_spectra must be >= 1");
+    if (h->n_held == 0 || n_spectra > h->n_held) return fail(h, CORR_E_STATE, "autotune needs held spectra");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(h->stream, &cs);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) return fail(h, CORR_E_STATE, "cannot autotune while capturing");
+    const int n_tb = (n_spectra + h->TB - 1) / h->TB;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find({h->prec, h->N, n_tb});
+        if (it != g_tune.end()) {
+            h->tile = it->second;
+            if (tile_out) *tile_out = h->tile;
+            return CORR_OK;
+        }
+    }
+    const int Ct = std::min(h->C, 256);
+    void *tmp = nullptr;
+    if ((e = hipMalloc(&tmp, (size_t)Ct * h->B * 8)) != hipSuccess) return hip_fail(h, e, "hipMalloc autotune");
+    hipEvent_t ev[2];
+    (void)hipEventCreate(&ev[0]);
+    (void)hipEventCreate(&ev[1]);
+    const int cand[2] = {64, 128};
+    float best_ms = 0;
+    int best = 0;
+    for (int c : cand) {
+        float ms = 0;
+        e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->n_tb_cap, h->spec, x_scale(h), tmp, 1, h->stream);
+        for (int r = 0; e == hipSuccess && r < 3; ++r) {
+            (void)hipEventRecord(ev[0], h->stream);
+            e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->n_tb_cap, h->spec, x_scale(h), tmp, 1,
+                               h->stream);
+            (void)hipEventRecord(ev[1], h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float t = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+            ms = (r == 0 || t < ms) ? t : ms;
+        }
+        if (e != hipSuccess) break;
+        if (!best || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(h, e, "autotune");
+    h->tile = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store_locked(h->prec, h->N, n_tb, best);
+    }
+    if (tile_out) *tile_out = best;
+    h->err.clear();
+    return CORR_OK;
+}
+
+static void destroy_batch(corr_batch *b) {
+    if (b->stream || !b->subs.empty()) (void)hipStreamSynchronize(b->stream);
+    for (corr_ctx *h : b->subs) destroy_ctx(h);
+    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_counter);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    delete b;
+}
+
+corr_status corr_create_batched(const corr_params *params, int32_t n, void *hip_stream, corr_batch_handle *out) {
+    if (!params || !out) return fail(nullptr, CORR_E_INVALID_ARG, "params and out must not be NULL");
+    if (n < 1 || n > 65536) return fail(nullptr, CORR_E_INVALID_ARG, "n must be in 1..65536");
+    std::string msg;
+    uint64_t need = 0;
+    for (int i = 0; i < n; ++i) {
+        corr_status s = check_params(&params[i], msg);
+        if (s != CORR_OK) return fail(nullptr, s, "sub-array " + std::to_string(i) + ": " + msg);
+        if (params[i].precision != params[0].precision)
+            return fail(nullptr, CORR_E_UNSUPPORTED, "all sub-arrays must share one precision");
+        const int64_t N = n_inputs(&params[i]);
+        const int TB = time_block(params[i].precision);
+        need += (uint64_t)params[i].n_channels * channel_stride((params[i].n_integrate + TB - 1) / TB, (int)N) +
+                (uint64_t)params[i].n_channels * (N * (N + 1) / 2) * 8;
+    }
+    if (params[0].device_mem_cap && need > params[0].device_mem_cap)
+        return fail(nullptr, CORR_E_NOMEM, "batch needs " + std::to_string(need) + " bytes, over the cap");
+    corr_batch *b = new (std::nothrow) corr_batch();
+    if (!b) return fail(nullptr, CORR_E_NOMEM, "host allocation failed");
+    b->prec = params[0].precision;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    for (int i = 0; i < n; ++i) {
+        corr_params p = params[i];
+        p.device_mem_cap = 0;
+        corr_handle h = nullptr;
+        corr_status s = corr_create(&p, hip_stream, &h);
+        if (s != CORR_OK) {
+            std::string m = "sub-array " + std::to_string(i) + ": " + g_err;
+            destroy_batch(b);
+            return fail(nullptr, s, m);
+        }
+        h->batch_member = true;
+        h->acc_zero = false;
+        b->subs.push_back(h);
+        hipError_t e = launch_zero(h->acc, (int64_t)(h->acc_bytes / 4), b->stream);
+        if (e != hipSuccess) {
+            destroy_batch(b);
+            return fail(nullptr, CORR_E_HIP, std::string("zero launch: ") + hipGetErrorString(e));
+        }
+    }
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipMalloc(&b->d_desc, sizeof(XDesc) * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_counter, sizeof(unsigned int));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_desc, sizeof(XDesc) * (size_t)n, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        destroy_batch(b);
+        return fail(nullptr, CORR_E_HIP, std::string("batch setup: ") + hipGetErrorString(e));
+    }
+    b->grid = 2 * (cus > 0 ? cus : 256);
+    *out = b;
+    return CORR_OK;
+}
+
+corr_status corr_batch_get(corr_batch_handle b, int32_t i, corr_handle *h) {
+    if (!b || !h) return fail(nullptr, CORR_E_INVALID_ARG, "batch and h must not be NULL");
+    if (i < 0 || i >= (int)b->subs.size()) return fail(nullptr, CORR_E_INVALID_ARG, "sub-array index out of range");
+    *h = b->subs[i];
+    return CORR_OK;
+}
+
+corr_status corr_xengine_batched(corr_batch_handle b, const int32_t *n_spectra) {
+    if (!b || !n_spectra) return fail(nullptr, CORR_E_INVALID_ARG, "batch and n_spectra must not be NULL");
+    const int n = (int)b->subs.size();
+    for (int i = 0; i < n; ++i) {
+        corr_ctx *h = b->subs[i];
+        const int ns = n_spectra[i];
+        if (ns < 0) return fail(nullptr, CORR_E_INVALID_ARG, "n_spectra must be >= 0");
+        if (ns == 0) continue;
+        if (h->n_held == 0 || ns > h->n_held)
+            return fail(nullptr, CORR_E_STATE, "sub-array " + std::to_string(i) + ": n_spectra exceeds held");
+        if (h->prec == P_INT8 && h->n_integrated + ns > CORR_INT8_MAX_INTEGRATE)
+            return fail(nullptr, CORR_E_OVERFLOW, "sub-array " + std::to_string(i) + ": int8 integration too long");
+    }
+    // descriptors, largest item first
+    std::vector<std::pair<int64_t, int>> order;
+    for (int i = 0; i < n; ++i) {
+        if (!n_spectra[i]) continue;
+        const corr_ctx *h = b->subs[i];
+        const int t = effective_tile(h);
+        const int64_t n_tb = (n_spectra[i] + h->TB - 1) / h->TB;
+        order.push_back({n_tb * t * t, i});
+    }
+    if (order.empty()) return CORR_OK;
+    std::stable_sort(order.begin(), order.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<XDesc> d;
+    int64_t items = 0;
+    for (const auto &o : order) {
+        const corr_ctx *h = b->subs[o.second];
+        const int ns = n_spectra[o.second];
+        XDesc x{};
+        x.spec = static_cast<const uint8_t *>(h->spec);
+        x.acc = h->acc;
+        x.scale2 = x_scale(h);
+        x.k_stride = channel_stride(h->n_tb_cap, h->N);
+        x.B = h->B;
+        x.item_begin = items;
+        x.N = h->N;
+        x.n_tb = (ns + h->TB - 1) / h->TB;
+        x.tv = ns - (x.n_tb - 1) * h->TB;
+        x.tile = effective_tile(h);
+        const int nb = (h->N + x.tile - 1) / x.tile;
+        x.n_tiles = nb * (nb + 1) / 2;
+        x.first_call = 0;                     // batch accumulators are always zero in memory after reset
+        items += (int64_t)h->C * x.n_tiles;
+        d.push_back(x);
+    }
+    if (items >= ((int64_t)1 << 31)) return fail(nullptr, CORR_E_UNSUPPORTED, "more than 2^31 work items");
+    hipError_t e;
+    const bool same = d.size() == b->last.size() && std::memcmp(d.data(), b->last.data(), d.size() * sizeof(XDesc)) == 0;
+    if (!same) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if ((e = hipStreamIsCapturing(b->stream, &cs)) != hipSuccess)
+            return fail(nullptr, CORR_E_HIP, std::string("hipStreamIsCapturing: ") + hipGetErrorString(e));
+        if (cs != hipStreamCaptureStatusNone)
+            return fail(nullptr, CORR_E_STATE, "the work list changed during graph capture; call once before capturing");
+        // the previous upload may still be reading the pinned staging buffer
+        if ((e = hipStreamSynchronize(b->stream)) != hipSuccess)
+            return fail(nullptr, CORR_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+        std::memcpy(b->h_desc, d.data(), d.size() * sizeof(XDesc));
+        if ((e = hipMemcpyAsync(b->d_desc, b->h_desc, d.size() * sizeof(XDesc), hipMemcpyHostToDevice, b->stream)) !=
+            hipSuccess)
+            return fail(nullptr, CORR_E_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+        b->last = d;
+    }
+    const int grid = (int)std::min<int64_t>(items, b->grid);
+    e = launch_xengine_batched(b->prec, b->d_desc, (int)d.size(), items, b->d_counter, grid, b->stream);
+    if (e != hipSuccess) return fail(nullptr, CORR_E_HIP, std::string("batched launch: ") + hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) {
+        if (!n_spectra[i]) continue;
+        b->subs[i]->n_integrated += n_spectra[i];
+        b->subs[i]->acc_zero = false;
+    }
+    return CORR_OK;
+}
+
+corr_status corr_destroy_batched(corr_batch_handle b) {
+    if (!b) return fail(nullptr, CORR_E_INVALID_ARG, "batch is NULL");
+    destroy_batch(b);
     return CORR_OK;
 }
 

@@ -55,10 +55,29 @@ hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t l
 
 // X-engine: accumulate Eq. 2 over the first n_spectra spectra of the spectra
 // buffer into acc (spectra past n_spectra in the last time block are masked to
-// zero).  scale2 (float forms, may be null = 1): per-channel s_k^2 applied to
-// the integrated products.  first_call = 1 writes instead of read-modify-write.
-hipError_t launch_xengine(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+// zero), with square blocks of `tile` (64 or 128) inputs.  scale2 (float
+// forms, may be null = 1): per-channel s_k^2 applied to the integrated
+// products.  first_call = 1 writes instead of read-modify-write.
+hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
                           const float *scale2, void *acc, int first_call, hipStream_t stream);
+
+// One sub-array of a batched X-engine launch.  Items [item_begin,
+// item_begin + C * n_tiles) are (channel, block) pairs of this sub-array.
+struct XDesc {
+    const uint8_t *spec;
+    void *acc;
+    const float *scale2;
+    int64_t k_stride;
+    int64_t B;
+    int64_t item_begin;
+    int N, n_tb, tv, tile, n_tiles, first_call;
+};
+
+// Persistent X-engine over n_desc sub-arrays (descriptors in device memory,
+// sorted by item cost, largest first): a one-thread kernel zeroes `counter`,
+// then `grid` workgroups drain the n_items work items.
+hipError_t launch_xengine_batched(int prec, const XDesc *d_desc, int n_desc, int64_t n_items,
+                                  unsigned int *counter, int grid, hipStream_t stream);
 
 // Public [A][C][N][2] spectra <-> internal layout (ingest zero-fills the tail
 // of the last time block).

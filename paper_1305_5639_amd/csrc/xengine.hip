@@ -44,10 +44,11 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXThreads = 256;
-constexpr int kTile = 128;
 constexpr int kRowStride = 144;                   // 2 planes x 64 B + 16 B pad
-constexpr int kOpBytes = kTile * kRowStride;
-constexpr int kStageBytes = 2 * kOpBytes;
+// LDS bytes of one operand slab and of one stage (two slabs) for a tile size.
+constexpr int op_bytes(int tile) { return tile * kRowStride; }
+constexpr int stage_bytes(int tile) { return 2 * op_bytes(tile); }
+constexpr int kMaxStageBytes = stage_bytes(128);
 
 // Per-precision fragment type and MFMA step.  A lane owns 32 bytes of each
 // (row, plane) per time block, read as KS fragments of FB bytes; each
@@ -117,92 +118,99 @@ template <> struct XT<P_FP8> {
     }
 };
 
-// One time block of a wave's 64x64 quarter: KS fragment reads per (row or
-// column half, plane), NSUB MFMAs per fragment, four real products per 32x32
-// block (Re += Ar Br + Ai Bi, Im += Ar Bi + Ai (-Br)), issued across both
-// column halves so dependent MFMAs are apart.  SKIP_UPPER: a diagonal wave
-// leaves out its upper 32x32 block (rows 0-31, columns 32-63).
-template <int PREC, bool SKIP_UPPER, typename Acc>
-__device__ __forceinline__ void wave_block(Acc (&re)[2][2], Acc (&im)[2][2], const uint8_t *pa,
+// One time block of a wave's quarter (FS x FS blocks of 32x32; FS = 2 for
+// 128-input tiles, 1 for 64-input tiles): KS fragment reads per (row or column
+// block, plane), NSUB MFMAs per fragment, four real products per 32x32 block
+// (Re += Ar Br + Ai Bi, Im += Ar Bi + Ai (-Br)), issued across the column
+// blocks so dependent MFMAs are apart.  SKIP_UPPER (FS = 2 only): a diagonal
+// wave leaves out its upper 32x32 block (rows 0-31, columns 32-63).
+template <int PREC, int FS, bool SKIP_UPPER, typename Acc>
+__device__ __forceinline__ void wave_block(Acc (&re)[FS][FS], Acc (&im)[FS][FS], const uint8_t *pa,
                                            const uint8_t *pb) {
     using X = XT<PREC>;
 #pragma unroll
     for (int s = 0; s < X::KS; ++s) {
-        typename X::Frag b[2][2], nb[2];
+        typename X::Frag b[FS][2], nb[FS];
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < FS; ++g) {
             b[g][0] = X::load(pb + g * 32 * kRowStride + s * X::FB);
             b[g][1] = X::load(pb + g * 32 * kRowStride + kRowBytes + s * X::FB);
             nb[g] = X::neg(b[g][0]);
         }
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
+        for (int f = 0; f < FS; ++f) {
             const typename X::Frag ar = X::load(pa + f * 32 * kRowStride + s * X::FB);
             const typename X::Frag ai = X::load(pa + f * 32 * kRowStride + kRowBytes + s * X::FB);
-            const bool up = SKIP_UPPER && f == 0;
 #pragma unroll
             for (int e = 0; e < X::NSUB; ++e) {
-                X::mfma(re[f][0], ar, b[0][0], e);                  // + xr_i xr_j
-                if (!up) X::mfma(re[f][1], ar, b[1][0], e);
-                X::mfma(im[f][0], ar, b[0][1], e);                  // + xr_i xi_j
-                if (!up) X::mfma(im[f][1], ar, b[1][1], e);
-                X::mfma(re[f][0], ai, b[0][1], e);                  // + xi_i xi_j
-                if (!up) X::mfma(re[f][1], ai, b[1][1], e);
-                X::mfma(im[f][0], ai, nb[0], e);                    // - xi_i xr_j
-                if (!up) X::mfma(im[f][1], ai, nb[1], e);
+#pragma unroll
+                for (int g = 0; g < FS; ++g)
+                    if (!(SKIP_UPPER && f < g)) X::mfma(re[f][g], ar, b[g][0], e);    // + xr_i xr_j
+#pragma unroll
+                for (int g = 0; g < FS; ++g)
+                    if (!(SKIP_UPPER && f < g)) X::mfma(im[f][g], ar, b[g][1], e);    // + xr_i xi_j
+#pragma unroll
+                for (int g = 0; g < FS; ++g)
+                    if (!(SKIP_UPPER && f < g)) X::mfma(re[f][g], ai, b[g][1], e);    // + xi_i xi_j
+#pragma unroll
+                for (int g = 0; g < FS; ++g)
+                    if (!(SKIP_UPPER && f < g)) X::mfma(im[f][g], ai, nb[g], e);      // - xi_i xr_j
             }
         }
     }
 }
 
-// The whole K loop and epilogue of one 128x128 block of channel k, rows
+// The whole K loop and epilogue of one TILE x TILE block of channel k, rows
 // I0.., columns J0...  Both operand slabs are always staged (a diagonal block
 // stages the same rows twice) so the staging code has no branches between
-// its global loads.
-template <int PREC>
+// its global loads.  4 waves, each owning a (TILE/2) x (TILE/2) quarter.
+template <int PREC, int TILE>
 __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ base_k, int N, int n_tb, int tv,
                                      int I0, int J0, int k, const float *__restrict__ scale2,
                                      void *__restrict__ acc_out, int64_t B, int first_call) {
     using Acc = typename XT<PREC>::Acc;
     constexpr int ES = PREC == P_FP32 ? 4 : (PREC == P_FP16 ? 2 : 1);
     constexpr int TB = kRowBytes / ES;
-    constexpr int NOP = 2;                              // operand slabs per stage
-    const bool DIAG = I0 == J0;
+    constexpr int QS = TILE / 2;                        // rows of a wave's quarter
+    constexpr int FS = QS / 32;                         // 32x32 blocks per quarter side
+    constexpr int U = TILE / 32;                        // 16-byte chunks per thread per slab
+    constexpr int OPB = op_bytes(TILE), STB = stage_bytes(TILE);
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wi = wave >> 1, wj = wave & 1;
     const int m = lane & 31, h = lane >> 5;
-    const bool active = !(DIAG && wj > wi);
-    const bool dwave = DIAG && wi == wj;     // diagonal wave: skip its upper 32x32 block
+    const bool diag = I0 == J0;
+    const bool active = !(diag && wj > wi);
+    const bool dwave = FS > 1 && diag && wi == wj;      // skip the upper 32x32 block
 
     // Global -> register staging of one time block.  The loads are issued
     // unconditionally (rows past N read row N-1) and nothing inspects the
     // registers until store_stage, which runs after the block's MFMAs, so the
     // loads stay in flight during the compute.  store_stage zeroes rows past N
     // and, in the last time block, spectra past the valid count.
-    uint4 st[4 * NOP];
+    uint4 st[2 * U];
     auto load_stage = [&](int tb) {
         const uint8_t *blk = base_k + (int64_t)tb * N * (2 * kRowBytes);
 #pragma unroll
-        for (int o = 0; o < NOP; ++o)
+        for (int o = 0; o < 2; ++o)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int c = tid + kXThreads * u;
                 const int row = c >> 3, col = c & 7;
                 const int pr = min((o ? J0 : I0) + row, N - 1);
-                st[4 * o + u] = *reinterpret_cast<const uint4 *>(blk + (int64_t)pr * (2 * kRowBytes) + col * 16);
+                st[U * o + u] = *reinterpret_cast<const uint4 *>(blk + (int64_t)pr * (2 * kRowBytes) + col * 16);
             }
     };
     auto store_stage = [&](int buf, int tb) {
-        uint8_t *sm = smem + buf * kStageBytes;
+        uint8_t *sm = smem + buf * STB;
         const bool tail = tb == n_tb - 1 && tv < TB;
 #pragma unroll
-        for (int o = 0; o < NOP; ++o)
+        for (int o = 0; o < 2; ++o)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int c = tid + kXThreads * u;
                 const int row = c >> 3, col = c & 7;
-                uint4 v = st[4 * o + u];
+                uint4 v = st[U * o + u];
                 if ((o ? J0 : I0) + row >= N) v = make_uint4(0, 0, 0, 0);
                 if (tail) {
                     // zero the spectra past the valid count in the last time block
@@ -217,15 +225,15 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
                         wd[d] &= msk;
                     }
                 }
-                *reinterpret_cast<uint4 *>(sm + o * kOpBytes + row * kRowStride + col * 16) = v;
+                *reinterpret_cast<uint4 *>(sm + o * OPB + row * kRowStride + col * 16) = v;
             }
     };
 
-    Acc re[2][2], im[2][2];
+    Acc re[FS][FS], im[FS][FS];
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < FS; ++f)
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < FS; ++g) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 re[f][g][r] = 0;
@@ -240,15 +248,15 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
         const bool more = tb + 1 < n_tb;
         if (more) load_stage(tb + 1);
         if (active) {
-            const uint8_t *sI = smem + (tb & 1) * kStageBytes;
-            const uint8_t *sJ = sI + kOpBytes;
-            const uint8_t *pa = sI + (wi * 64 + m) * kRowStride + h * 32;
-            const uint8_t *pb = sJ + (wj * 64 + m) * kRowStride + h * 32;
+            const uint8_t *sI = smem + (tb & 1) * STB;
+            const uint8_t *sJ = sI + OPB;
+            const uint8_t *pa = sI + (wi * QS + m) * kRowStride + h * 32;
+            const uint8_t *pb = sJ + (wj * QS + m) * kRowStride + h * 32;
             // one uniform branch per block keeps the MFMA stream branch-free
             if (dwave)
-                wave_block<PREC, true>(re, im, pa, pb);
+                wave_block<PREC, FS, true>(re, im, pa, pb);
             else
-                wave_block<PREC, false>(re, im, pa, pb);
+                wave_block<PREC, FS, false>(re, im, pa, pb);
         }
         if (more) store_stage((tb + 1) & 1, tb + 1);
         __syncthreads();
@@ -262,16 +270,16 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     T2 *out = reinterpret_cast<T2 *>(acc_out) + (int64_t)k * B;
     const float s2 = (PREC != P_INT8 && scale2) ? scale2[k] : 1.0f;
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < FS; ++f)
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < FS; ++g) {
             if (dwave && f < g) continue;
-            const int j = J0 + wj * 64 + g * 32 + m;
+            const int j = J0 + wj * QS + g * 32 + m;
             int64_t idx[16];
             uint32_t ok = 0;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int i = I0 + wi * 64 + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 const bool in = i < N && j <= i;
                 ok |= (uint32_t)in << r;
                 idx[r] = in ? (int64_t)i * (i + 1) / 2 + j : 0;
@@ -283,7 +291,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int i = I0 + wi * 64 + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 T2 v;
                 if constexpr (PREC == P_INT8) {
                     v = make_int2(re[f][g][r], i == j ? 0 : im[f][g][r]);
@@ -299,55 +307,135 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
         }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void xengine_kernel(
+// Lower-triangle block t of a tiling with blocks (bi, bj), bj <= bi, in the
+// order (0,0), (1,0), (1,1), (2,0), ...
+__device__ __forceinline__ void tri_block(int t, int &bi, int &bj) {
+    int b = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (b * (b + 1) / 2 > t) --b;
+    while ((b + 1) * (b + 2) / 2 <= t) ++b;
+    bi = b;
+    bj = t - b * (b + 1) / 2;
+}
+
+template <int PREC, int TILE>
+__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) void xengine_kernel(
     const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
     int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, int64_t B,
     int first_call) {
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * kStageBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * stage_bytes(TILE)];
     const int per = (n_work + 7) / 8;
     const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (w >= n_work) return;
     const int k = w / n_tiles;
-    const int t = w % n_tiles;
-    int bi = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-    while (bi * (bi + 1) / 2 > t) --bi;
-    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-    const int bj = t - bi * (bi + 1) / 2;
-    const uint8_t *base_k = spec + (int64_t)k * k_stride;
-    tile<PREC>(smem, base_k, N, n_tb, tv, bi * kTile, bj * kTile, k, scale2, acc_out, B, first_call);
+    int bi, bj;
+    tri_block(w % n_tiles, bi, bj);
+    tile<PREC, TILE>(smem, spec + (int64_t)k * k_stride, N, n_tb, tv, bi * TILE, bj * TILE, k, scale2, acc_out,
+                     B, first_call);
 }
 
+// Persistent X-engine over many sub-arrays: every workgroup takes work items
+// (sub-array, channel, block) from an atomic counter until the list is
+// exhausted, so uneven sub-arrays share one launch.  Descriptors are sorted by
+// the cost of one item, largest first, and each descriptor's items are
+// contiguous; a workgroup finds its descriptor by binary search.
 template <int PREC>
+__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void xengine_batched_kernel(
+    const XDesc *__restrict__ desc, int n_desc, int64_t n_items, unsigned int *__restrict__ counter) {
+    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * kMaxStageBytes];
+    __shared__ int64_t s_item;
+    const int tid = threadIdx.x;
+    while (true) {
+        if (tid == 0) s_item = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();                                // s_item and smem free for reuse
+        if (item >= n_items) break;
+        int lo = 0, hi = n_desc - 1;                    // last descriptor with begin <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (desc[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+        }
+        const XDesc d = desc[lo];
+        const int64_t local = item - d.item_begin;
+        const int k = (int)(local / d.n_tiles);
+        int bi, bj;
+        tri_block((int)(local % d.n_tiles), bi, bj);
+        const uint8_t *base_k = d.spec + (int64_t)k * d.k_stride;
+        if (d.tile == 64)
+            tile<PREC, 64>(smem, base_k, d.N, d.n_tb, d.tv, bi * 64, bj * 64, k, d.scale2, d.acc, d.B,
+                           d.first_call);
+        else
+            tile<PREC, 128>(smem, base_k, d.N, d.n_tb, d.tv, bi * 128, bj * 128, k, d.scale2, d.acc, d.B,
+                            d.first_call);
+    }
+}
+
+__global__ void reset_counter_kernel(unsigned int *counter) { *counter = 0u; }
+
+template <int PREC, int TILE>
 hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
                     void *acc, int first_call, hipStream_t stream) {
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
     const int tv = n_spectra - (n_tb - 1) * TB;
-    const int n_blk = (N + kTile - 1) / kTile;
+    const int n_blk = (N + TILE - 1) / TILE;
     const int n_tiles = n_blk * (n_blk + 1) / 2;
     const int64_t n_work = (int64_t)C * n_tiles;
     if (n_tb <= 0 || n_work <= 0 || n_work > ((int64_t)1 << 30)) return hipErrorInvalidValue;
     const int grid = (int)((n_work + 7) / 8) * 8;
     const int64_t k_stride = channel_stride(n_tb_cap, N);
     const int64_t B = (int64_t)N * (N + 1) / 2;
-    hipLaunchKernelGGL(xengine_kernel<PREC>, dim3(grid), dim3(kXThreads), 0, stream,
+    hipLaunchKernelGGL((xengine_kernel<PREC, TILE>), dim3(grid), dim3(kXThreads), 0, stream,
                        static_cast<const uint8_t *>(spec), N, n_tiles, (int)n_work, n_tb, tv, k_stride,
                        scale2, acc, B, first_call);
     return hipGetLastError();
 }
 
+template <int PREC>
+hipError_t launch_xp(int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
+                     void *acc, int first_call, hipStream_t stream) {
+    if (tile == 64) return launch_x<PREC, 64>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    if (tile == 128) return launch_x<PREC, 128>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-hipError_t launch_xengine(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
                           const float *scale2, void *acc, int first_call, hipStream_t stream) {
     switch (prec) {
-    case P_FP32: return launch_x<P_FP32>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
-    case P_FP16: return launch_x<P_FP16>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
-    case P_FP8: return launch_x<P_FP8>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
-    case P_INT8: return launch_x<P_INT8>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    case P_FP32: return launch_xp<P_FP32>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    case P_FP16: return launch_xp<P_FP16>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    case P_FP8: return launch_xp<P_FP8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    case P_INT8: return launch_xp<P_INT8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_xengine_batched(int prec, const XDesc *d_desc, int n_desc, int64_t n_items,
+                                  unsigned int *counter, int grid, hipStream_t stream) {
+    if (n_desc <= 0 || n_items <= 0 || n_items >= ((int64_t)1 << 31) || grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+    switch (prec) {
+    case P_FP32:
+        hipLaunchKernelGGL(xengine_batched_kernel<P_FP32>, dim3(grid), dim3(kXThreads), 0, stream, d_desc, n_desc,
+                           n_items, counter);
+        break;
+    case P_FP16:
+        hipLaunchKernelGGL(xengine_batched_kernel<P_FP16>, dim3(grid), dim3(kXThreads), 0, stream, d_desc, n_desc,
+                           n_items, counter);
+        break;
+    case P_FP8:
+        hipLaunchKernelGGL(xengine_batched_kernel<P_FP8>, dim3(grid), dim3(kXThreads), 0, stream, d_desc, n_desc,
+                           n_items, counter);
+        break;
+    case P_INT8:
+        hipLaunchKernelGGL(xengine_batched_kernel<P_INT8>, dim3(grid), dim3(kXThreads), 0, stream, d_desc, n_desc,
+                           n_items, counter);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace corr

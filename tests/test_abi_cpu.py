@@ -140,3 +140,31 @@ def test_error_raises_with_status():
     with pytest.raises(corr.CorrError) as ei:
         corr.corr_create(corr.make_params(3, 5, 64, 8))
     assert ei.value.status == corr.CORR_E_INVALID_ARG
+
+
+def test_batched_rejects_on_cpu():
+    L = corr.lib()
+    b = ctypes.c_void_p()
+    good = corr.make_params(4, 2, 64, 16, "fp16", device_mem_cap=1 << 40)
+    mixed = corr.make_params(4, 2, 64, 16, "int8", device_mem_cap=1 << 40)
+    bad = corr.make_params(4, 3, 64, 16, "fp16", device_mem_cap=1 << 40)
+    arr = (corr.corr_params * 2)(good, mixed)
+    assert L.corr_create_batched(arr, 2, None, ctypes.byref(b)) == corr.CORR_E_UNSUPPORTED
+    arr = (corr.corr_params * 2)(good, bad)
+    assert L.corr_create_batched(arr, 2, None, ctypes.byref(b)) == corr.CORR_E_INVALID_ARG
+    assert "sub-array 1" in corr.corr_last_error(None)
+    small = corr.make_params(4, 2, 64, 16, "fp16", device_mem_cap=1000)
+    arr = (corr.corr_params * 2)(small, good)
+    assert L.corr_create_batched(arr, 2, None, ctypes.byref(b)) == corr.CORR_E_NOMEM
+    arr = (corr.corr_params * 1)(good)
+    assert L.corr_create_batched(arr, 0, None, ctypes.byref(b)) == corr.CORR_E_INVALID_ARG
+    assert L.corr_create_batched(None, 1, None, ctypes.byref(b)) == corr.CORR_E_INVALID_ARG
+    assert b.value is None
+    h = ctypes.c_void_p()
+    assert L.corr_batch_get(None, 0, ctypes.byref(h)) == corr.CORR_E_INVALID_ARG
+    n = (ctypes.c_int32 * 1)(1)
+    assert L.corr_xengine_batched(None, n) == corr.CORR_E_INVALID_ARG
+    assert L.corr_destroy_batched(None) == corr.CORR_E_INVALID_ARG
+    assert L.corr_set_tile(None, 64) == corr.CORR_E_INVALID_ARG
+    t = ctypes.c_int32()
+    assert L.corr_autotune(None, 1, ctypes.byref(t)) == corr.CORR_E_INVALID_ARG

@@ -1,0 +1,146 @@
+"""GPU parity of the block-size variants, the autotuner and the batched
+persistent X-engine (one launch over uneven sub-arrays), including replay of
+a captured HIP graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1305_5639_amd as corr
+import synth
+from helpers import cplx, say, spectra_akp_to_apk, vis_errors
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("N,C,A", [(1, 16, 5), (33, 16, 65), (64, 32, 64), (100, 16, 130), (130, 16, 70),
+                                   (200, 16, 33)])
+def test_tile_sizes_int8_bit_exact(tile, N, C, A):
+    say(f"tile {tile} int8 N={N} C={C} A={A}")
+    S = synth.int8_spectra(A, C, N, seed=N + tile + A)
+    with corr.Correlator(N, 1, C, A, "int8") as c:
+        c.set_tile(tile)
+        c.xengine(A, torch.from_numpy(S).to(DEV))
+        got = c.dump().cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, oracle.xengine_i8(spectra_akp_to_apk(S)))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "fp8"])
+def test_tile64_float_forms(prec):
+    N, C, A = 70, 16, 96
+    say(f"tile 64 {prec}")
+    q = np.clip(synth.int8_spectra(A, C, N, seed=3, rms=3.0), -8, 8).astype(np.float64)
+    t = torch.from_numpy(q).to(corr.SPECTRA_DTYPE[corr.PRECISIONS[prec]]).to(DEV)
+    with corr.Correlator(N, 1, C, A, prec) as c:
+        c.set_tile(64)
+        c.xengine(A, t)
+        got = cplx(c.dump().cpu().numpy())
+    ref = oracle.xengine_f64(spectra_akp_to_apk(cplx(q)))
+    eF, en = vis_errors(got, ref, N)
+    assert eF.max() < 1e-6 and en.max() < 1e-6
+
+
+def test_autotune_picks_a_tile_and_keeps_parity():
+    N, C, A = 90, 32, 64
+    say("autotune")
+    S = synth.int8_spectra(A, C, N, seed=17)
+    with corr.Correlator(N, 1, C, A, "int8") as c:
+        c.xengine(A, torch.from_numpy(S).to(DEV))          # holds the spectra (and integrates once)
+        tile = c.autotune(A)
+        assert tile in (64, 128)
+        assert c.autotune(A) == tile                        # cached
+        c.xengine(A)                                         # second integration with the tuned tile
+        got = c.dump().cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, 2 * oracle.xengine_i8(spectra_akp_to_apk(S)))
+
+
+SHAPES = [(1, 2, 16, 40), (16, 2, 32, 100), (35, 2, 16, 64), (65, 2, 16, 70), (100, 1, 64, 33), (150, 2, 16, 50)]
+
+
+def _batch_inputs(prec, shapes, seed=0):
+    vs, invs = [], []
+    for r, (ns, npol, C, A) in enumerate(shapes):
+        w = synth.small(f"b{r}", ns, npol, C, A, seed=seed + r)
+        vs.append(synth.voltages(w))
+        invs.append(synth.inv_scale(w, prec))
+    return vs, invs
+
+
+@pytest.mark.parametrize("tiles", ["auto", "mixed"])
+def test_batched_int8_bit_exact(tiles):
+    say(f"batched int8 {tiles}")
+    vs, invs = _batch_inputs("int8", SHAPES)
+    with corr.Batch(SHAPES, "int8") as b:
+        for i, sub in enumerate(b.subs):
+            if tiles == "mixed":
+                sub.set_tile(64 if i % 2 else 128)
+            sub.fengine(torch.from_numpy(vs[i]).to(DEV), SHAPES[i][3], torch.from_numpy(invs[i]).to(DEV))
+        n = [A for (_, _, _, A) in SHAPES]
+        n[2] = 0                                             # sub-array 2 skipped this call
+        n[4] = 17                                            # a prefix of the held spectra
+        b.xengine(n)
+        for i, sub in enumerate(b.subs):
+            sp = sub.spectra().cpu().numpy()
+            got = sub.dump().cpu().numpy().astype(np.int64)
+            if n[i] == 0:
+                assert not got.any()
+                continue
+            ref = oracle.xengine_i8(spectra_akp_to_apk(sp[: n[i]]))
+            assert np.array_equal(got, ref), i
+
+
+def test_batched_matches_standalone_fp16_and_resumes():
+    say("batched fp16 vs standalone")
+    vs, invs = _batch_inputs("fp16", SHAPES, seed=10)
+    n = [A for (_, _, _, A) in SHAPES]
+    with corr.Batch(SHAPES, "fp16") as b:
+        for i, sub in enumerate(b.subs):
+            sub.fengine(torch.from_numpy(vs[i]).to(DEV), n[i], torch.from_numpy(invs[i]).to(DEV))
+        b.xengine(n)
+        b.xengine(n)                                         # integrates twice
+        got = [sub.dump(reset=True).cpu().numpy() for sub in b.subs]
+        b.xengine(n)                                         # after the reset: once
+        once = [sub.dump(reset=True).cpu().numpy() for sub in b.subs]
+    for i, (ns, npol, C, A) in enumerate(SHAPES):
+        with corr.Correlator(ns, npol, C, A, "fp16") as c:
+            c.fengine(torch.from_numpy(vs[i]).to(DEV), A, torch.from_numpy(invs[i]).to(DEV))
+            c.xengine(A)
+            ref = cplx(c.dump().cpu().numpy())
+        N = ns * npol
+        eF, en = vis_errors(cplx(got[i]), 2 * ref, N)
+        assert eF.max() < 1e-6 and en.max() < 1e-6, i
+        eF, en = vis_errors(cplx(once[i]), ref, N)
+        assert eF.max() < 1e-6 and en.max() < 1e-6, i
+
+
+def test_batched_graph_replay_matches_eager():
+    """F-engines and the persistent X-engine captured in one graph; every replay
+    (with eager dumps and synchronisations between) equals the eager result."""
+    say("batched graph replay")
+    shapes = SHAPES[:4]
+    vs, invs = _batch_inputs("int8", shapes, seed=20)
+    stream = torch.cuda.Stream()
+    n = [A for (_, _, _, A) in shapes]
+    with torch.cuda.stream(stream):
+        vd = [torch.from_numpy(v).to(DEV) for v in vs]
+        idd = [torch.from_numpy(x).to(DEV) for x in invs]
+        b = corr.Batch(shapes, "int8", stream=stream)
+        for i, sub in enumerate(b.subs):
+            sub.fengine(vd[i], n[i], idd[i])
+        b.xengine(n)                                         # eager reference (also fixes the work list)
+        ref = [sub.dump(reset=True).cpu().numpy() for sub in b.subs]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for i, sub in enumerate(b.subs):
+                sub.fengine(vd[i], n[i], idd[i])
+            b.xengine(n)
+        for rep in range(3):
+            g.replay()
+            stream.synchronize()
+            got = [sub.dump(reset=True).cpu().numpy() for sub in b.subs]
+            for i in range(len(shapes)):
+                assert np.array_equal(got[i], ref[i]), (rep, i)
+            torch.zeros(1000, device=DEV).sum().item()       # unrelated eager work between replays
+        b.close()
