@@ -58,9 +58,36 @@ def parse():
     ap.add_argument("--cpu-channels", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "xengine_traffic.json"),
-                    help="HBM bytes per X-engine launch measured with rocprofv3 counters")
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "xengine_fp32_mwa-128x2-c1024_traffic.txt"),
+                    help="rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the X-engine (HBM bytes per launch)")
     return ap.parse_args()
+
+
+def source_hash(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(path, key):
+    """HBM bytes per X-engine launch from a rocprofv3 counter summary, or None
+    when the summary is missing or was taken on a different X-engine source.
+    Lines read: 'xengine_source_sha256_16 = <hash>' and
+    'traffic_bytes_per_launch <workload>/<precision> = <bytes>'."""
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for l in lines:
+        if "=" in l:
+            k, v = l.split("=", 1)
+            vals[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1305_5639_amd", "csrc", "xengine.hip")
+    if vals.get("xengine_source_sha256_16") != source_hash(src):
+        return None
+    v = vals.get(f"traffic_bytes_per_launch {key}")
+    return float(v) if v else None
 
 
 def log(msg):
@@ -237,8 +264,8 @@ def run_batched(torch, corr, synth, steps_per_integration, reps=3):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(the multi-GPU frequency split is a design only)"}))
+        print(json.dumps({"error": "the correlator runs on one GPU; --gpus must be 1 "
+                          "(splitting channels across GPUs is not implemented)"}))
         print("bench.py: only --gpus 1 is supported", file=sys.stderr)
         return 2
 
@@ -279,15 +306,7 @@ def main():
 
     x_flops = 8.0 * cmacs
     x_achieved = x_flops / (x_ms * 1e-3) / 1e12
-    traffic = None
-    try:
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        key = f"{w.name}/{prec}"
-        if key in tj:
-            traffic = tj[key]
-    except (OSError, ValueError):
-        pass
+    traffic = read_traffic(args.traffic_file, f"{w.name}/{prec}")
     roofline = {"kernel": f"xengine_kernel<{prec}>", "bound": "mfma", "achieved": x_achieved,
                 "peak": PEAK[prec], "unit": "TFLOP/s", "frac": x_achieved / PEAK[prec],
                 "traffic": traffic}

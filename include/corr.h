@@ -193,9 +193,10 @@ CORR_API corr_status corr_get_counts(corr_handle h, int32_t *n_held, int64_t *n_
 
 /*
  * X-engine block size.  The triangle of each channel is covered by square
- * blocks of `tile` inputs (64 or 128); 0 selects by N (64 for N <= 64, else
- * 128) unless corr_autotune has chosen.  Larger blocks reuse each operand
- * more; smaller ones waste less on the diagonal and on ragged N.
+ * blocks of `tile` inputs (64 or 128); 0 selects a default unless
+ * corr_autotune has chosen: 64 for FP32, int8, N <= 64 and FP8 with
+ * N <= 256, else 128.  Larger blocks reuse each operand more; smaller ones
+ * run more workgroups per CU and waste less on the diagonal and on ragged N.
  */
 CORR_API corr_status corr_set_tile(corr_handle h, int32_t tile);
 
@@ -212,8 +213,9 @@ CORR_API corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *ti
 
 /*
  * Batched form: many sub-arrays of uneven size (stations, channels,
- * integration) correlated by ONE persistent X-engine launch that drains a
- * work list of (sub-array, channel, block) items, largest first.  All
+ * integration) correlated by persistent X-engine launches -- one per block
+ * size in use, so at most two -- that drain a work list of (sub-array,
+ * channel, block) items, largest first.  All
  * sub-arrays share one precision and stream.  Each sub-array is an ordinary
  * handle owned by the batch (corr_batch_get): use corr_fengine,
  * corr_dump_visibilities and corr_autotune on it as usual; corr_destroy on it

@@ -49,11 +49,11 @@ struct corr_batch {
     std::vector<corr_ctx *> subs;
     int prec = 0;
     hipStream_t stream = nullptr;
-    int grid = 0;                     // persistent workgroups (2 per CU)
-    XDesc *d_desc = nullptr;          // device descriptors
-    XDesc *h_desc = nullptr;          // pinned staging of the descriptors
-    std::vector<XDesc> last;          // descriptors last uploaded
-    unsigned int *d_counter = nullptr;
+    int num_cus = 0;                  // compute units of the device
+    uint8_t *d_plan = nullptr;        // device work plan: XQueue[2], then XDesc[n]
+    uint8_t *h_plan = nullptr;        // pinned staging of the plan
+    std::vector<uint8_t> last;        // plan last uploaded
+    unsigned int *d_counter = nullptr;  // per-XCD work counters of both block-size groups
     std::string err;
 };
 
@@ -141,7 +141,16 @@ bool default_dump(const corr_params *p) { return p->layout == CORR_TRI_LOWER && 
 
 bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
-int effective_tile(const corr_ctx *h) { return h->tile ? h->tile : (h->N <= 64 ? 64 : 128); }
+// Default block size when none was set or tuned, from measured X-engine
+// speed on MI355X at 256..1024 inputs: 64-input blocks (four workgroups per
+// CU) win for FP32 and int8, and for FP8 up to 256 inputs; 128-input blocks
+// (more operand reuse) win for FP16 and for larger FP8 arrays.
+int effective_tile(const corr_ctx *h) {
+    if (h->tile) return h->tile;
+    if (h->N <= 64 || h->prec == P_FP32 || h->prec == P_INT8) return 64;
+    if (h->prec == P_FP8 && h->N <= 256) return 64;
+    return 128;
+}
 
 const float *x_scale(const corr_ctx *h) {
     if (h->prec == P_INT8) return nullptr;
@@ -542,12 +551,17 @@ corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile_out) {
     return CORR_OK;
 }
 
+// Bytes of a batch work plan for n sub-arrays: two group headers, then the
+// descriptors of both groups.
+static_assert(sizeof(XQueue) % alignof(XDesc) == 0, "descriptors follow the two headers");
+static size_t plan_size(int n) { return 2 * sizeof(XQueue) + (size_t)n * sizeof(XDesc); }
+
 static void destroy_batch(corr_batch *b) {
     if (b->stream || !b->subs.empty()) (void)hipStreamSynchronize(b->stream);
     for (corr_ctx *h : b->subs) destroy_ctx(h);
-    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_plan);
     (void)hipFree(b->d_counter);
-    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    if (b->h_plan) (void)hipHostFree(b->h_plan);
     delete b;
 }
 
@@ -594,14 +608,15 @@ corr_status corr_create_batched(const corr_params *params, int32_t n, void *hip_
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipMalloc(&b->d_desc, sizeof(XDesc) * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc(&b->d_counter, sizeof(unsigned int));
-    if (e == hipSuccess) e = hipHostMalloc(&b->h_desc, sizeof(XDesc) * (size_t)n, hipHostMallocDefault);
+    const size_t plan_bytes = plan_size(n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_plan, plan_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b->d_counter, 2 * kXcds * kCounterStride * sizeof(unsigned int));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_plan, plan_bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
         destroy_batch(b);
         return fail(nullptr, CORR_E_HIP, std::string("batch setup: ") + hipGetErrorString(e));
     }
-    b->grid = 2 * (cus > 0 ? cus : 256);
+    b->num_cus = cus > 0 ? cus : 256;
     *out = b;
     return CORR_OK;
 }
@@ -626,43 +641,59 @@ corr_status corr_xengine_batched(corr_batch_handle b, const int32_t *n_spectra) 
         if (h->prec == P_INT8 && h->n_integrated + ns > CORR_INT8_MAX_INTEGRATE)
             return fail(nullptr, CORR_E_OVERFLOW, "sub-array " + std::to_string(i) + ": int8 integration too long");
     }
-    // descriptors, largest item first
-    std::vector<std::pair<int64_t, int>> order;
+    // descriptors in two groups (64- then 128-input blocks), each largest item
+    // first; XCD x's queue of a group takes channels [x C/8, (x+1) C/8) of each
+    // of its sub-arrays in that order
+    std::vector<std::pair<int64_t, int>> order[2];
     for (int i = 0; i < n; ++i) {
         if (!n_spectra[i]) continue;
         const corr_ctx *h = b->subs[i];
         const int t = effective_tile(h);
         const int64_t n_tb = (n_spectra[i] + h->TB - 1) / h->TB;
-        order.push_back({n_tb * t * t, i});
+        order[t == 64 ? 0 : 1].push_back({n_tb * t * t, i});
     }
-    if (order.empty()) return CORR_OK;
-    std::stable_sort(order.begin(), order.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    if (order[0].empty() && order[1].empty()) return CORR_OK;
+    XQueue q[2] = {};
     std::vector<XDesc> d;
-    int64_t items = 0;
-    for (const auto &o : order) {
-        const corr_ctx *h = b->subs[o.second];
-        const int ns = n_spectra[o.second];
-        XDesc x{};
-        x.spec = static_cast<const uint8_t *>(h->spec);
-        x.acc = h->acc;
-        x.scale2 = x_scale(h);
-        x.k_stride = channel_stride(h->n_tb_cap, h->N);
-        x.B = h->B;
-        x.item_begin = items;
-        x.N = h->N;
-        x.n_tb = (ns + h->TB - 1) / h->TB;
-        x.tv = ns - (x.n_tb - 1) * h->TB;
-        x.tile = effective_tile(h);
-        const int nb = (h->N + x.tile - 1) / x.tile;
-        x.n_tiles = nb * (nb + 1) / 2;
-        x.first_call = 0;                     // batch accumulators are always zero in memory after reset
-        items += (int64_t)h->C * x.n_tiles;
-        d.push_back(x);
+    for (int g = 0; g < 2; ++g) {
+        std::stable_sort(order[g].begin(), order[g].end(),
+                         [](const auto &x, const auto &y) { return x.first > y.first; });
+        q[g].n_desc = (int)order[g].size();
+        q[g].desc_offset = (int)d.size();
+        for (const auto &o : order[g]) {
+            const corr_ctx *h = b->subs[o.second];
+            const int ns = n_spectra[o.second];
+            XDesc x{};
+            x.spec = static_cast<const uint8_t *>(h->spec);
+            x.acc = h->acc;
+            x.scale2 = x_scale(h);
+            x.k_stride = channel_stride(h->n_tb_cap, h->N);
+            x.B = h->B;
+            x.C = h->C;
+            x.N = h->N;
+            x.n_tb = (ns + h->TB - 1) / h->TB;
+            x.tv = ns - (x.n_tb - 1) * h->TB;
+            x.tile = effective_tile(h);
+            const int nb = (h->N + x.tile - 1) / x.tile;
+            x.n_tiles = nb * (nb + 1) / 2;
+            x.first_call = 0;                 // batch accumulators are always zero in memory after reset
+            for (int xc = 0; xc < kXcds; ++xc) {
+                x.qbegin[xc] = q[g].qlen[xc];
+                const int c_lo = xc * h->C / kXcds, c_hi = (xc + 1) * h->C / kXcds;
+                q[g].qlen[xc] += (int64_t)(c_hi - c_lo) * x.n_tiles;
+            }
+            d.push_back(x);
+        }
+        for (int xc = 0; xc < kXcds; ++xc)
+            if (q[g].qlen[xc] >= ((int64_t)1 << 31))
+                return fail(nullptr, CORR_E_UNSUPPORTED, "more than 2^31 work items on one XCD");
     }
-    if (items >= ((int64_t)1 << 31)) return fail(nullptr, CORR_E_UNSUPPORTED, "more than 2^31 work items");
+    const size_t bytes = plan_size((int)d.size());
+    std::vector<uint8_t> plan(bytes);
+    std::memcpy(plan.data(), q, sizeof(q));
+    std::memcpy(plan.data() + sizeof(q), d.data(), d.size() * sizeof(XDesc));
     hipError_t e;
-    const bool same = d.size() == b->last.size() && std::memcmp(d.data(), b->last.data(), d.size() * sizeof(XDesc)) == 0;
-    if (!same) {
+    if (plan != b->last) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if ((e = hipStreamIsCapturing(b->stream, &cs)) != hipSuccess)
             return fail(nullptr, CORR_E_HIP, std::string("hipStreamIsCapturing: ") + hipGetErrorString(e));
@@ -671,14 +702,15 @@ corr_status corr_xengine_batched(corr_batch_handle b, const int32_t *n_spectra) 
         // the previous upload may still be reading the pinned staging buffer
         if ((e = hipStreamSynchronize(b->stream)) != hipSuccess)
             return fail(nullptr, CORR_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
-        std::memcpy(b->h_desc, d.data(), d.size() * sizeof(XDesc));
-        if ((e = hipMemcpyAsync(b->d_desc, b->h_desc, d.size() * sizeof(XDesc), hipMemcpyHostToDevice, b->stream)) !=
-            hipSuccess)
-            return fail(nullptr, CORR_E_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
-        b->last = d;
+        std::memcpy(b->h_plan, plan.data(), bytes);
+        if ((e = hipMemcpyAsync(b->d_plan, b->h_plan, bytes, hipMemcpyHostToDevice, b->stream)) != hipSuccess)
+            return fail(nullptr, CORR_E_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+        b->last.swap(plan);
     }
-    const int grid = (int)std::min<int64_t>(items, b->grid);
-    e = launch_xengine_batched(b->prec, b->d_desc, (int)d.size(), items, b->d_counter, grid, b->stream);
+    const int groups = (q[0].n_desc ? 1 : 0) | (q[1].n_desc ? 2 : 0);
+    e = launch_xengine_batched(b->prec, reinterpret_cast<const XQueue *>(b->d_plan),
+                               reinterpret_cast<const XDesc *>(b->d_plan + 2 * sizeof(XQueue)), groups,
+                               b->d_counter, b->num_cus, b->stream);
     if (e != hipSuccess) return fail(nullptr, CORR_E_HIP, std::string("batched launch: ") + hipGetErrorString(e));
     for (int i = 0; i < n; ++i) {
         if (!n_spectra[i]) continue;

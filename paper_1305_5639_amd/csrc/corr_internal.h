@@ -63,21 +63,43 @@ hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n
 
 // One sub-array of a batched X-engine launch.  Items [item_begin,
 // item_begin + C * n_tiles) are (channel, block) pairs of this sub-array.
+// Accelerator complex dies (XCDs), each with its own L2; workgroups are
+// dispatched to them round-robin by workgroup index.
+constexpr int kXcds = 8;
+// Work counters of the batched X-engine sit kCounterStride words apart (256
+// bytes), one per cache line; 2 x 8 of them.
+constexpr int kCounterStride = 64;
+
 struct XDesc {
     const uint8_t *spec;
     void *acc;
     const float *scale2;
     int64_t k_stride;
     int64_t B;
-    int64_t item_begin;
-    int N, n_tb, tv, tile, n_tiles, first_call;
+    int64_t qbegin[kXcds];            // offset of this sub-array's items in each XCD's queue
+    int C, N, n_tb, tv, tile, n_tiles, first_call, pad;
 };
 
-// Persistent X-engine over n_desc sub-arrays (descriptors in device memory,
-// sorted by item cost, largest first): a one-thread kernel zeroes `counter`,
-// then `grid` workgroups drain the n_items work items.
-hipError_t launch_xengine_batched(int prec, const XDesc *d_desc, int n_desc, int64_t n_items,
-                                  unsigned int *counter, int grid, hipStream_t stream);
+// Work plan of one block-size group, resident in device memory beside the
+// descriptors it indexes (so a kernel never pairs queue lengths from one
+// upload with descriptors from another).
+struct XQueue {
+    int64_t qlen[kXcds];              // items in each XCD's queue
+    int n_desc;                       // descriptors of the group
+    int desc_offset;                  // index of the group's first descriptor
+};
+
+// Persistent X-engine over sub-arrays in two groups by block size (plan[0]:
+// 64-input blocks, plan[1]: 128-input blocks; descriptors of each group sorted
+// by item cost, largest first).  XCD x's queue holds channels
+// [x C/8, (x+1) C/8) of every sub-array of the group, in descriptor order.
+// Workgroups take items from their own XCD's queue, then from the others,
+// through per-queue atomic counters.  A 16-thread kernel zeroes the 2 x 8 counters
+// (2 * kXcds * kCounterStride words), then one persistent launch per group in
+// launch_group (bit 0: 64-input, bit 1: 128-input) runs at that block size's
+// occupancy.
+hipError_t launch_xengine_batched(int prec, const XQueue *d_plan, const XDesc *d_desc, int launch_group,
+                                  unsigned int *counters, int num_cus, hipStream_t stream);
 
 // Public [A][C][N][2] spectra <-> internal layout (ingest zero-fills the tail
 // of the last time block).

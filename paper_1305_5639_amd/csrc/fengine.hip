@@ -199,22 +199,12 @@ __device__ __forceinline__ void fft(float2 *v, float2 *lds, const float2 *__rest
 }
 
 // ---- requantisation --------------------------------------------------------
-// OCP E4M3, round half to even, saturating at +-448.  a / 2^q is exact, so the
-// only rounding is rintf (round half to even).
+// OCP E4M3 (gfx950's FP8 format), round half to even, saturating at +-448: the
+// value is clamped to the largest finite E4M3 magnitude first, so the
+// hardware conversion (round to nearest even) never overflows.
 __device__ __forceinline__ uint8_t to_e4m3(float y) {
     y = fminf(fmaxf(y, -448.0f), 448.0f);
-    const uint32_t u = __float_as_uint(y);
-    const uint8_t sign = (uint8_t)((u >> 31) << 7);
-    const float a = fabsf(y);
-    int e = (int)((u >> 23) & 0xff) - 127;       // exponent of the leading bit (a normal float)
-    if (e < -6) e = -6;                          // E4M3 subnormals share the quantum 2^-9
-    const int q = e - 3;
-    int m = (int)rintf(ldexpf(a, -q));            // 0..16
-    if (m == 0) return sign;                      // +-0
-    int E = q + 10;                               // field for m in [8, 16)
-    if (m >= 16) { m = 8; E += 1; }               // rounded up into the next binade
-    if (m < 8) return sign | (uint8_t)m;          // subnormal (only when q == -9)
-    return sign | (uint8_t)(E << 3) | (uint8_t)(m - 8);
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(y, y, 0, false) & 0xff);
 }
 
 template <int PREC> struct Elem;

@@ -29,6 +29,7 @@
 // The epilogue scales by s_k^2 (float forms) and adds into the persistent
 // lower-triangle accumulators (or writes them on the first call of an
 // integration); autos get an exactly zero imaginary part, as Eq. 2 gives.
+#include <algorithm>
 #include <type_traits>
 
 #include "corr_internal.h"
@@ -42,6 +43,16 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Device-memory pointers in the global address space.  Loads and stores
+// through them compile to global_* instructions even where the pointer was
+// itself read from memory (a descriptor); a generic pointer would give flat_*
+// instructions, which also count against the LDS wait counter and so make
+// every LDS wait drain the prefetch loads as well.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const uint8_t gu8;
+typedef __attribute__((address_space(1))) const u32x4 gu4;
+typedef __attribute__((address_space(1))) const float gf32;
 
 constexpr int kXThreads = 256;
 constexpr int kRowStride = 144;                   // 2 planes x 64 B + 16 B pad
@@ -167,7 +178,7 @@ __device__ __forceinline__ void wave_block(Acc (&re)[FS][FS], Acc (&im)[FS][FS],
 template <int PREC, int TILE>
 __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ base_k, int N, int n_tb, int tv,
                                      int I0, int J0, int k, const float *__restrict__ scale2,
-                                     void *__restrict__ acc_out, int64_t B, int first_call) {
+                                     void *__restrict__ acc_out, int64_t B, int first_call, int tid) {
     using Acc = typename XT<PREC>::Acc;
     constexpr int ES = PREC == P_FP32 ? 4 : (PREC == P_FP16 ? 2 : 1);
     constexpr int TB = kRowBytes / ES;
@@ -175,7 +186,6 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     constexpr int FS = QS / 32;                         // 32x32 blocks per quarter side
     constexpr int U = TILE / 32;                        // 16-byte chunks per thread per slab
     constexpr int OPB = op_bytes(TILE), STB = stage_bytes(TILE);
-    const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wi = wave >> 1, wj = wave & 1;
     const int m = lane & 31, h = lane >> 5;
@@ -189,8 +199,9 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     // loads stay in flight during the compute.  store_stage zeroes rows past N
     // and, in the last time block, spectra past the valid count.
     uint4 st[2 * U];
+    gu8 *const gbase = (gu8 *)base_k;
     auto load_stage = [&](int tb) {
-        const uint8_t *blk = base_k + (int64_t)tb * N * (2 * kRowBytes);
+        gu8 *blk = gbase + (int64_t)tb * N * (2 * kRowBytes);
 #pragma unroll
         for (int o = 0; o < 2; ++o)
 #pragma unroll
@@ -198,7 +209,8 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
                 const int c = tid + kXThreads * u;
                 const int row = c >> 3, col = c & 7;
                 const int pr = min((o ? J0 : I0) + row, N - 1);
-                st[U * o + u] = *reinterpret_cast<const uint4 *>(blk + (int64_t)pr * (2 * kRowBytes) + col * 16);
+                const u32x4 q = *(gu4 *)(blk + (int64_t)pr * (2 * kRowBytes) + col * 16);
+                st[U * o + u] = make_uint4(q.x, q.y, q.z, q.w);
             }
     };
     auto store_stage = [&](int buf, int tb) {
@@ -266,9 +278,11 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     // Epilogue: element r of a 32x32 block is (row 8(r/4) + 4h + r%4, column m).
     // All of a block's accumulator reads are issued before any write; elements
     // outside the triangle or past N read a valid address and are not written.
-    using T2 = typename std::conditional<PREC == P_INT8, int2, float2>::type;
-    T2 *out = reinterpret_cast<T2 *>(acc_out) + (int64_t)k * B;
-    const float s2 = (PREC != P_INT8 && scale2) ? scale2[k] : 1.0f;
+    using E = typename std::conditional<PREC == P_INT8, int, float>::type;
+    typedef E T2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) T2 gT2;
+    gT2 *out = (gT2 *)acc_out + (int64_t)k * B;
+    const float s2 = (PREC != P_INT8 && scale2) ? ((gf32 *)scale2)[k] : 1.0f;
 #pragma unroll
     for (int f = 0; f < FS; ++f)
 #pragma unroll
@@ -294,9 +308,9 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
                 const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 T2 v;
                 if constexpr (PREC == P_INT8) {
-                    v = make_int2(re[f][g][r], i == j ? 0 : im[f][g][r]);
+                    v = T2{re[f][g][r], i == j ? 0 : im[f][g][r]};
                 } else {
-                    v = make_float2(re[f][g][r] * s2, i == j ? 0.0f : im[f][g][r] * s2);
+                    v = T2{re[f][g][r] * s2, i == j ? 0.0f : im[f][g][r] * s2};
                 }
                 if (!first_call) {
                     v.x += old[r].x;
@@ -330,47 +344,68 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     int bi, bj;
     tri_block(w % n_tiles, bi, bj);
     tile<PREC, TILE>(smem, spec + (int64_t)k * k_stride, N, n_tb, tv, bi * TILE, bj * TILE, k, scale2, acc_out,
-                     B, first_call);
+                     B, first_call, threadIdx.x);
 }
 
-// Persistent X-engine over many sub-arrays: every workgroup takes work items
-// (sub-array, channel, block) from an atomic counter until the list is
-// exhausted, so uneven sub-arrays share one launch.  Descriptors are sorted by
-// the cost of one item, largest first, and each descriptor's items are
-// contiguous; a workgroup finds its descriptor by binary search.
-template <int PREC>
-__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void xengine_batched_kernel(
-    const XDesc *__restrict__ desc, int n_desc, int64_t n_items, unsigned int *__restrict__ counter) {
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * kMaxStageBytes];
-    __shared__ int64_t s_item;
+// Persistent X-engine over many sub-arrays with blocks of TILE inputs, so
+// uneven sub-arrays share one launch.  Work items are (sub-array, channel,
+// block); XCD x's queue holds channels [x C/8, (x+1) C/8) of every sub-array,
+// so the blocks of one channel run on one XCD and share its L2.  A workgroup
+// takes items from its own XCD's queue through that queue's atomic counter
+// (the ticket for the next item is taken while the current one runs), and
+// once it is drained from the other queues in turn; every workgroup ends
+// after one failed take on each of the eight queues.  Within a queue the
+// descriptors follow their sorted order (largest item first) and a workgroup
+// finds its descriptor by binary search over the queue offsets.
+template <int PREC, int TILE>
+__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(TILE == 64 ? 4 : 2))) void xengine_batched_kernel(
+    const XQueue *__restrict__ plan, const XDesc *__restrict__ all_desc, unsigned int *__restrict__ counter) {
+    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * stage_bytes(TILE)];
+    __shared__ unsigned int s_item;
     const int tid = threadIdx.x;
-    while (true) {
-        if (tid == 0) s_item = (int64_t)atomicAdd(counter, 1u);
+    const int n_desc = plan->n_desc;
+    const XDesc *__restrict__ desc = all_desc + plan->desc_offset;
+    const int home = blockIdx.x % kXcds;
+    for (int s = 0; s < kXcds; ++s) {
+        const int x = (home + s) % kXcds;
+        unsigned int *cnt = counter + x * kCounterStride;
+        const int64_t qlen = plan->qlen[x];
+        if (tid == 0) s_item = atomicAdd(cnt, 1u);
         __syncthreads();
-        const int64_t item = s_item;
-        __syncthreads();                                // s_item and smem free for reuse
-        if (item >= n_items) break;
-        int lo = 0, hi = n_desc - 1;                    // last descriptor with begin <= item
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (desc[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+        // uniform across the workgroup: keep it (and the descriptor fields it
+        // selects) in scalar registers
+        int64_t item = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_item);
+        __syncthreads();                                // s_item free for reuse
+        while (item < qlen) {
+            // take the next ticket now; its latency overlaps this item's loads
+            unsigned int next = 0;
+            if (tid == 0) next = atomicAdd(cnt, 1u);
+            int lo = 0, hi = n_desc - 1;                // last descriptor with qbegin[x] <= item
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (desc[mid].qbegin[x] <= item) lo = mid; else hi = mid - 1;
+            }
+            const XDesc &d = desc[lo];
+            const int64_t local = item - d.qbegin[x];
+            const int k = x * d.C / kXcds + (int)(local / d.n_tiles);
+            int bi, bj;
+            tri_block((int)(local % d.n_tiles), bi, bj);
+            // an opaque copy of the thread index keeps the block body's
+            // per-lane address arithmetic inside the loop instead of live
+            // across it (which cost registers and occupancy)
+            int t = tid;
+            asm volatile("" : "+v"(t));
+            tile<PREC, TILE>(smem, d.spec + (int64_t)k * d.k_stride, d.N, d.n_tb, d.tv, bi * TILE, bj * TILE, k,
+                             d.scale2, d.acc, d.B, d.first_call, t);
+            if (tid == 0) s_item = next;
+            __syncthreads();                            // also: every wave is done with smem
+            item = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_item);
+            __syncthreads();
         }
-        const XDesc d = desc[lo];
-        const int64_t local = item - d.item_begin;
-        const int k = (int)(local / d.n_tiles);
-        int bi, bj;
-        tri_block((int)(local % d.n_tiles), bi, bj);
-        const uint8_t *base_k = d.spec + (int64_t)k * d.k_stride;
-        if (d.tile == 64)
-            tile<PREC, 64>(smem, base_k, d.N, d.n_tb, d.tv, bi * 64, bj * 64, k, d.scale2, d.acc, d.B,
-                           d.first_call);
-        else
-            tile<PREC, 128>(smem, base_k, d.N, d.n_tb, d.tv, bi * 128, bj * 128, k, d.scale2, d.acc, d.B,
-                            d.first_call);
     }
 }
 
-__global__ void reset_counter_kernel(unsigned int *counter) { *counter = 0u; }
+__global__ void reset_counters_kernel(unsigned int *counter) { counter[threadIdx.x * kCounterStride] = 0u; }
 
 template <int PREC, int TILE>
 hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
@@ -412,30 +447,40 @@ hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n
     }
 }
 
-hipError_t launch_xengine_batched(int prec, const XDesc *d_desc, int n_desc, int64_t n_items,
-                                  unsigned int *counter, int grid, hipStream_t stream) {
-    if (n_desc <= 0 || n_items <= 0 || n_items >= ((int64_t)1 << 31) || grid <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+template <int PREC, int TILE>
+hipError_t launch_batched_t(const XQueue *d_plan, const XDesc *d_desc, unsigned int *counter, int grid,
+                            hipStream_t stream) {
+    hipLaunchKernelGGL((xengine_batched_kernel<PREC, TILE>), dim3(grid), dim3(kXThreads), 0, stream, d_plan, d_desc,
+                       counter);
+    return hipGetLastError();
+}
+
+template <int TILE>
+hipError_t launch_batched_p(int prec, const XQueue *d_plan, const XDesc *d_desc, unsigned int *counter, int grid,
+                            hipStream_t stream) {
     switch (prec) {
-    case P_FP32:
-        hipLaunchKernelGGL(xengine_batched_kernel<P_FP32>, dim3(grid), dim3(kXThreads), 0, stream, d_desc, n_desc,
-                           n_items, counter);
-        break;
-    case P_FP16:
-        hipLaunchKernelGGL(xengine_batched_kernel<P_FP16>, dim3(grid), dim3(kXThreads), 0, stream, d_desc, n_desc,
-                           n_items, counter);
-        break;
-    case P_FP8:
-        hipLaunchKernelGGL(xengine_batched_kernel<P_FP8>, dim3(grid), dim3(kXThreads), 0, stream, d_desc, n_desc,
-                           n_items, counter);
-        break;
-    case P_INT8:
-        hipLaunchKernelGGL(xengine_batched_kernel<P_INT8>, dim3(grid), dim3(kXThreads), 0, stream, d_desc, n_desc,
-                           n_items, counter);
-        break;
+    case P_FP32: return launch_batched_t<P_FP32, TILE>(d_plan, d_desc, counter, grid, stream);
+    case P_FP16: return launch_batched_t<P_FP16, TILE>(d_plan, d_desc, counter, grid, stream);
+    case P_FP8: return launch_batched_t<P_FP8, TILE>(d_plan, d_desc, counter, grid, stream);
+    case P_INT8: return launch_batched_t<P_INT8, TILE>(d_plan, d_desc, counter, grid, stream);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+hipError_t launch_xengine_batched(int prec, const XQueue *d_plan, const XDesc *d_desc, int launch_group,
+                                  unsigned int *counters, int num_cus, hipStream_t stream) {
+    if (num_cus <= 0 || (launch_group & ~3)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(2 * kXcds), 0, stream, counters);
+    hipError_t e = hipGetLastError();
+    // 128-input blocks first (the larger items), two workgroups per CU; then
+    // 64-input blocks, four workgroups per CU.
+    // (grids rounded to a multiple of the XCD count, as the kernel assumes)
+    const int g128 = std::max(kXcds, 2 * num_cus / kXcds * kXcds), g64 = std::max(kXcds, 4 * num_cus / kXcds * kXcds);
+    if (e == hipSuccess && (launch_group & 2))
+        e = launch_batched_p<128>(prec, d_plan + 1, d_desc, counters + kXcds * kCounterStride, g128, stream);
+    if (e == hipSuccess && (launch_group & 1))
+        e = launch_batched_p<64>(prec, d_plan, d_desc, counters, g64, stream);
+    return e;
 }
 
 }  // namespace corr
