@@ -55,7 +55,7 @@ def parse():
                     help="skip the 64-sub-array batched (persistent, graph-captured) section")
     ap.add_argument("--batched-steps", type=int, default=8,
                     help="graph replays per integration in the batched section")
-    ap.add_argument("--cpu-channels", type=int, default=32)
+    ap.add_argument("--cpu-channels", type=int, default=768)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "xengine_fp32_mwa-128x2-c1024_traffic.txt"),
