@@ -194,8 +194,8 @@ CORR_API corr_status corr_get_counts(corr_handle h, int32_t *n_held, int64_t *n_
 /*
  * X-engine block size.  The triangle of each channel is covered by square
  * blocks of `tile` inputs (64 or 128); 0 selects a default unless
- * corr_autotune has chosen: 64 for FP32, int8, N <= 64 and FP8 with
- * N <= 256, else 128.  Larger blocks reuse each operand more; smaller ones
+ * corr_autotune has chosen: 64 for FP32, for N <= 64, and for int8 and FP8
+ * with N <= 256; else 128.  Larger blocks reuse each operand more; smaller ones
  * run more workgroups per CU and waste less on the diagonal and on ragged N.
  */
 CORR_API corr_status corr_set_tile(corr_handle h, int32_t tile);

@@ -143,12 +143,12 @@ bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
 // Default block size when none was set or tuned, from measured X-engine
 // speed on MI355X at 256..1024 inputs: 64-input blocks (four workgroups per
-// CU) win for FP32 and int8, and for FP8 up to 256 inputs; 128-input blocks
-// (more operand reuse) win for FP16 and for larger FP8 arrays.
+// CU) win for FP32, and for int8 and FP8 up to 256 inputs; 128-input blocks
+// (more operand reuse) win for FP16 and for larger int8 and FP8 arrays.
 int effective_tile(const corr_ctx *h) {
     if (h->tile) return h->tile;
-    if (h->N <= 64 || h->prec == P_FP32 || h->prec == P_INT8) return 64;
-    if (h->prec == P_FP8 && h->N <= 256) return 64;
+    if (h->N <= 64 || h->prec == P_FP32) return 64;
+    if ((h->prec == P_INT8 || h->prec == P_FP8) && h->N <= 256) return 64;
     return 128;
 }
 

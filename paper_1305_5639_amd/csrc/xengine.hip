@@ -55,191 +55,257 @@ typedef __attribute__((address_space(1))) const u32x4 gu4;
 typedef __attribute__((address_space(1))) const float gf32;
 
 constexpr int kXThreads = 256;
-constexpr int kRowStride = 144;                   // 2 planes x 64 B + 16 B pad
-// LDS bytes of one operand slab and of one stage (two slabs) for a tile size.
-constexpr int op_bytes(int tile) { return tile * kRowStride; }
-constexpr int stage_bytes(int tile) { return 2 * op_bytes(tile); }
-constexpr int kMaxStageBytes = stage_bytes(128);
+// LDS ring.  A stage is one time block of the TILE rows of both operand
+// slabs: 128-byte rows (both planes), two slots.  Rows have no padding; the
+// 16-byte chunk c of row r sits in slot c ^ swz(r).  A 16-byte-per-lane LDS
+// read is served 16 lanes (16 consecutive rows here) per cycle from 64 banks
+// of 4 bytes; swz makes those 16 rows cover all 64 banks.  A lane's fragment
+// of one (row, plane) and stage is kNT = 2 chunks (32 bytes).
+constexpr int kRB = 2 * kRowBytes;                     // LDS row bytes
+constexpr int kCPP = kRowBytes / 16;                   // 16-byte chunks per plane
+constexpr int kNT = 2;                                 // chunks per lane fragment
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & 7; }
+// LDS of a block: two ring slots of 2 TILE rows.
+constexpr int ring_bytes(int tile) { return 2 * 2 * tile * kRB; }
 
-// Per-precision fragment type and MFMA step.  A lane owns 32 bytes of each
-// (row, plane) per time block, read as KS fragments of FB bytes; each
-// fragment feeds NSUB MFMAs (sub-element e of the fragment).
-template <int PREC> struct XT;
+// Per-precision fragment type and MFMA step for NT chunks per lane.  A
+// fragment feeds NSUB MFMAs (sub-step e of the fragment).  The same chunk to
+// K-slot assignment is used for both operands, so which spectra share an MFMA
+// does not matter.
+template <int PREC, int NT> struct XT;
 
-template <> struct XT<P_FP32> {
+template <int NT> struct XT<P_FP32, NT> {
     using Acc = f32x16;
-    using Frag = f32x4;   // 4 spectra; 16-byte LDS reads are bank-conflict free
-    static constexpr int KS = 2, FB = 16, NSUB = 4;
-    static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const f32x4 *>(p); }
+    typedef float Frag __attribute__((ext_vector_type(4 * NT)));   // 4 NT spectra
+    static constexpr int NSUB = 4 * NT;
+    static __device__ __forceinline__ Frag load(const uint8_t *p, const int *o) {
+        Frag f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const f32x4 v = *reinterpret_cast<const f32x4 *>(p + o[t]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[4 * t + i] = v[i];
+        }
+        return f;
+    }
     static __device__ __forceinline__ Frag neg(Frag b) { return -b; }
     static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int e) {
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], c, 0, 0, 0);
     }
 };
 
-template <> struct XT<P_FP16> {
+// FP16 and int8 share the integer fragment: NT x 16 bytes, one MFMA per chunk.
+template <int PREC, int NT> struct XTInt {
+    typedef int Frag __attribute__((ext_vector_type(4 * NT)));
+    static constexpr int NSUB = NT;
+    static __device__ __forceinline__ Frag load(const uint8_t *p, const int *o) {
+        Frag f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const i32x4 v = *reinterpret_cast<const i32x4 *>(p + o[t]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[4 * t + i] = v[i];
+        }
+        return f;
+    }
+    static __device__ __forceinline__ i32x4 part(const Frag &f, int e) {
+        return i32x4{f[4 * e], f[4 * e + 1], f[4 * e + 2], f[4 * e + 3]};
+    }
+};
+
+template <int NT> struct XT<P_FP16, NT> : XTInt<P_FP16, NT> {
     using Acc = f32x16;
-    using Frag = i32x4;
-    static constexpr int KS = 2, FB = 16, NSUB = 1;
-    static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const i32x4 *>(p); }
-    static __device__ __forceinline__ Frag neg(Frag b) {
-        return Frag{b[0] ^ (int)0x80008000u, b[1] ^ (int)0x80008000u, b[2] ^ (int)0x80008000u,
-                    b[3] ^ (int)0x80008000u};
-    }
-    static __device__ __forceinline__ f16x8 h8(Frag x) { return __builtin_bit_cast(f16x8, x); }
-    static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int) {
-        c = __builtin_amdgcn_mfma_f32_32x32x16_f16(h8(a), h8(b), c, 0, 0, 0);
+    using Frag = typename XTInt<P_FP16, NT>::Frag;
+    static __device__ __forceinline__ Frag neg(Frag b) { return b ^ (int)0x80008000u; }
+    static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int e) {
+        c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, XTInt<P_FP16, NT>::part(a, e)),
+                                                   __builtin_bit_cast(f16x8, XTInt<P_FP16, NT>::part(b, e)), c, 0,
+                                                   0, 0);
     }
 };
 
-template <> struct XT<P_INT8> {
+template <int NT> struct XT<P_INT8, NT> : XTInt<P_INT8, NT> {
     using Acc = i32x16;
-    using Frag = i32x4;
-    static constexpr int KS = 2, FB = 16, NSUB = 1;
-    static __device__ __forceinline__ Frag load(const uint8_t *p) { return *reinterpret_cast<const i32x4 *>(p); }
-    // Byte-wise 0 - b without borrows between bytes.
-    static __device__ __forceinline__ int neg4(int v) {
-        const uint32_t x = (uint32_t)v;
-        return (int)((0x80808080u - (x & 0x7f7f7f7fu)) ^ (~x & 0x80808080u));
+    using Frag = typename XTInt<P_INT8, NT>::Frag;
+    // Byte-wise 0 - b without borrows between bytes (exact: the range is +-127).
+    static __device__ __forceinline__ Frag neg(Frag b) {
+        return (Frag)((0x80808080u - ((__typeof__(b))b & 0x7f7f7f7f)) ^ (~b & (int)0x80808080u));
     }
-    static __device__ __forceinline__ Frag neg(Frag b) { return Frag{neg4(b[0]), neg4(b[1]), neg4(b[2]), neg4(b[3])}; }
-    static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int) {
-        c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+    static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int e) {
+        c = __builtin_amdgcn_mfma_i32_32x32x32_i8(XTInt<P_INT8, NT>::part(a, e), XTInt<P_INT8, NT>::part(b, e), c,
+                                                  0, 0, 0);
     }
 };
 
-template <> struct XT<P_FP8> {
+template <int NT> struct XT<P_FP8, NT> {
+    static_assert(NT == 2, "the FP8 MFMA takes 32 bytes per lane");
     using Acc = f32x16;
     using Frag = i32x8;
-    static constexpr int KS = 1, FB = 32, NSUB = 1;
-    static __device__ __forceinline__ Frag load(const uint8_t *p) {
-        const i32x4 a = *reinterpret_cast<const i32x4 *>(p);
-        const i32x4 b = *reinterpret_cast<const i32x4 *>(p + 16);
+    static constexpr int NSUB = 1;
+    static __device__ __forceinline__ Frag load(const uint8_t *p, const int *o) {
+        const i32x4 a = *reinterpret_cast<const i32x4 *>(p + o[0]);
+        const i32x4 b = *reinterpret_cast<const i32x4 *>(p + o[1]);
         return Frag{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
     }
-    static __device__ __forceinline__ Frag neg(Frag b) {
-        Frag r;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) r[t] = b[t] ^ (int)0x80808080u;
-        return r;
-    }
+    static __device__ __forceinline__ Frag neg(Frag b) { return b ^ (int)0x80808080u; }
     // Format code 0 = FP8 E4M3 for both operands; E8M0 scale 127 = 2^0.
     static __device__ __forceinline__ void mfma(Acc &c, const Frag &a, const Frag &b, int) {
         c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
     }
 };
 
-// One time block of a wave's quarter (FS x FS blocks of 32x32; FS = 2 for
-// 128-input tiles, 1 for 64-input tiles): KS fragment reads per (row or column
-// block, plane), NSUB MFMAs per fragment, four real products per 32x32 block
-// (Re += Ar Br + Ai Bi, Im += Ar Bi + Ai (-Br)), issued across the column
-// blocks so dependent MFMAs are apart.  SKIP_UPPER (FS = 2 only): a diagonal
-// wave leaves out its upper 32x32 block (rows 0-31, columns 32-63).
-template <int PREC, int FS, bool SKIP_UPPER, typename Acc>
-__device__ __forceinline__ void wave_block(Acc (&re)[FS][FS], Acc (&im)[FS][FS], const uint8_t *pa,
-                                           const uint8_t *pb) {
-    using X = XT<PREC>;
-#pragma unroll
-    for (int s = 0; s < X::KS; ++s) {
-        typename X::Frag b[FS][2], nb[FS];
+// A wave's fragments of one stage: for each of its FS row blocks (a) and FS
+// column blocks (b), one fragment per plane.  pa / pb point at the lane's row
+// in the stage; off[plane] are the lane's swizzled chunk offsets in a row.
+template <int PREC, int FS, int NT> struct Frags {
+    using X = XT<PREC, NT>;
+    typename X::Frag a[FS][2], b[FS][2];
+    __device__ __forceinline__ void load(const uint8_t *pa, const uint8_t *pb, const int (&off)[2][NT]) {
+        constexpr int RB = kRB;
 #pragma unroll
         for (int g = 0; g < FS; ++g) {
-            b[g][0] = X::load(pb + g * 32 * kRowStride + s * X::FB);
-            b[g][1] = X::load(pb + g * 32 * kRowStride + kRowBytes + s * X::FB);
-            nb[g] = X::neg(b[g][0]);
+            b[g][0] = X::load(pb + g * 32 * RB, off[0]);
+            b[g][1] = X::load(pb + g * 32 * RB, off[1]);
         }
 #pragma unroll
         for (int f = 0; f < FS; ++f) {
-            const typename X::Frag ar = X::load(pa + f * 32 * kRowStride + s * X::FB);
-            const typename X::Frag ai = X::load(pa + f * 32 * kRowStride + kRowBytes + s * X::FB);
+            a[f][0] = X::load(pa + f * 32 * RB, off[0]);
+            a[f][1] = X::load(pa + f * 32 * RB, off[1]);
+        }
+    }
+};
+
+// The MFMAs of one stage of a wave's quarter (FS x FS blocks of 32x32; FS = 2
+// for 128-input tiles, 1 for 64-input tiles): NSUB MFMAs per fragment, four
+// real products per 32x32 block (Re += Ar Br + Ai Bi, Im += Ar Bi + Ai (-Br)),
+// issued across the column blocks so dependent MFMAs are apart.  SKIP_UPPER
+// (FS = 2 only): a diagonal wave leaves out its upper 32x32 block (rows 0-31,
+// columns 32-63).
+template <int PREC, int FS, int NT, bool SKIP_UPPER, typename Acc>
+__device__ __forceinline__ void wave_mfma(Acc (&re)[FS][FS], Acc (&im)[FS][FS], const Frags<PREC, FS, NT> &q) {
+    using X = XT<PREC, NT>;
+    typename X::Frag nb[FS];
 #pragma unroll
-            for (int e = 0; e < X::NSUB; ++e) {
+    for (int g = 0; g < FS; ++g) nb[g] = X::neg(q.b[g][0]);
 #pragma unroll
-                for (int g = 0; g < FS; ++g)
-                    if (!(SKIP_UPPER && f < g)) X::mfma(re[f][g], ar, b[g][0], e);    // + xr_i xr_j
+    for (int f = 0; f < FS; ++f) {
 #pragma unroll
-                for (int g = 0; g < FS; ++g)
-                    if (!(SKIP_UPPER && f < g)) X::mfma(im[f][g], ar, b[g][1], e);    // + xr_i xi_j
+        for (int e = 0; e < X::NSUB; ++e) {
 #pragma unroll
-                for (int g = 0; g < FS; ++g)
-                    if (!(SKIP_UPPER && f < g)) X::mfma(re[f][g], ai, b[g][1], e);    // + xi_i xi_j
+            for (int g = 0; g < FS; ++g)
+                if (!(SKIP_UPPER && f < g)) X::mfma(re[f][g], q.a[f][0], q.b[g][0], e);    // + xr_i xr_j
 #pragma unroll
-                for (int g = 0; g < FS; ++g)
-                    if (!(SKIP_UPPER && f < g)) X::mfma(im[f][g], ai, nb[g], e);      // - xi_i xr_j
-            }
+            for (int g = 0; g < FS; ++g)
+                if (!(SKIP_UPPER && f < g)) X::mfma(im[f][g], q.a[f][0], q.b[g][1], e);    // + xr_i xi_j
+#pragma unroll
+            for (int g = 0; g < FS; ++g)
+                if (!(SKIP_UPPER && f < g)) X::mfma(re[f][g], q.a[f][1], q.b[g][1], e);    // + xi_i xi_j
+#pragma unroll
+            for (int g = 0; g < FS; ++g)
+                if (!(SKIP_UPPER && f < g)) X::mfma(im[f][g], q.a[f][1], nb[g], e);        // - xi_i xr_j
         }
     }
 }
 
+// Asynchronous copy of 16 bytes per lane from global memory into LDS at
+// lds + 16 * lane (the LDS address is taken from M0).  Issued as inline
+// assembly so that the compiler, which cannot tell ring slots apart, does not
+// wait for every copy in flight before each LDS read; completion is awaited
+// explicitly with wait_vm.  The kernels here give the compiler no other use
+// of M0.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void dma16(gu8 *src, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds)
+                 : "memory", "m0");
+}
+
+#pragma clang diagnostic pop
+
+// Wait until at most n vector-memory operations of this wave are in flight.
+template <int n> __device__ __forceinline__ void wait_vm() {
+    static_assert(n >= 0 && n < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+
 // The whole K loop and epilogue of one TILE x TILE block of channel k, rows
-// I0.., columns J0...  Both operand slabs are always staged (a diagonal block
-// stages the same rows twice) so the staging code has no branches between
-// its global loads.  4 waves, each owning a (TILE/2) x (TILE/2) quarter.
+// I0.., columns J0..; 4 waves, each owning a (TILE/2) x (TILE/2) quarter.
+// Time blocks stream through a two-slot LDS ring by direct global-to-LDS
+// copies: the copy of time block t + 1 is issued when block t starts and
+// lands while its MFMAs run.  The copies bypass registers, so the block
+// keeps two workgroups per CU with the accumulators and fragments of a
+// 64x64 quarter per wave.  Both operand slabs are
+// always copied (a diagonal block copies the same rows twice).  Rows past N
+// copy row N - 1; they only feed outputs that are not written.  In the last
+// time block, spectra past the valid count are zeroed in LDS once it lands.
 template <int PREC, int TILE>
 __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ base_k, int N, int n_tb, int tv,
                                      int I0, int J0, int k, const float *__restrict__ scale2,
                                      void *__restrict__ acc_out, int64_t B, int first_call, int tid) {
-    using Acc = typename XT<PREC>::Acc;
+    constexpr int NT = kNT, RB = kRB, CPP = kCPP;
+    using Acc = typename XT<PREC, NT>::Acc;
     constexpr int ES = PREC == P_FP32 ? 4 : (PREC == P_FP16 ? 2 : 1);
     constexpr int TB = kRowBytes / ES;
     constexpr int QS = TILE / 2;                        // rows of a wave's quarter
     constexpr int FS = QS / 32;                         // 32x32 blocks per quarter side
-    constexpr int U = TILE / 32;                        // 16-byte chunks per thread per slab
-    constexpr int OPB = op_bytes(TILE), STB = stage_bytes(TILE);
+    constexpr int OPB = TILE * RB;                      // one operand slab of a stage
+    constexpr int STG = 2 * OPB;                        // one stage
+    constexpr int L = STG / (4 * 1024);                 // 1 KB copies per wave per stage
+    static_assert(2 * STG == ring_bytes(TILE) && L < 64, "ring geometry");
     const int wave = tid >> 6, lane = tid & 63;
     const int wi = wave >> 1, wj = wave & 1;
     const int m = lane & 31, h = lane >> 5;
     const bool diag = I0 == J0;
     const bool active = !(diag && wj > wi);
     const bool dwave = FS > 1 && diag && wi == wj;      // skip the upper 32x32 block
+    const int S = n_tb;                                 // stages
 
-    // Global -> register staging of one time block.  The loads are issued
-    // unconditionally (rows past N read row N-1) and nothing inspects the
-    // registers until store_stage, which runs after the block's MFMAs, so the
-    // loads stay in flight during the compute.  store_stage zeroes rows past N
-    // and, in the last time block, spectra past the valid count.
-    uint4 st[2 * U];
+    // Copy j of this wave covers stage bytes [g KB, (g + 1) KB), g = 4 j + wave;
+    // lane l writes bytes 16 l of it: slab o, row r, slot sl, which holds
+    // chunk c = sl ^ swz(r), i.e. bytes [16 (c % CPP), +16) of plane c / CPP.
+    int rowoff[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const int bo = (4 * j + wave) * 1024 + 16 * lane;
+        const int o = bo / OPB, r = (bo % OPB) / RB, c = ((bo % RB) / 16) ^ swz(r);
+        const int pr = min((o ? J0 : I0) + r, N - 1);
+        rowoff[j] = pr * RB + (c / CPP) * kRowBytes + (c % CPP) * 16;
+    }
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)smem;
     gu8 *const gbase = (gu8 *)base_k;
-    auto load_stage = [&](int tb) {
-        gu8 *blk = gbase + (int64_t)tb * N * (2 * kRowBytes);
+    auto issue = [&](int t) {
+        gu8 *src = gbase + (int64_t)t * N * RB;
+        const uint32_t dst = lds0 + (uint32_t)((t & 1) * STG);
 #pragma unroll
-        for (int o = 0; o < 2; ++o)
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = tid + kXThreads * u;
-                const int row = c >> 3, col = c & 7;
-                const int pr = min((o ? J0 : I0) + row, N - 1);
-                const u32x4 q = *(gu4 *)(blk + (int64_t)pr * (2 * kRowBytes) + col * 16);
-                st[U * o + u] = make_uint4(q.x, q.y, q.z, q.w);
-            }
+        for (int j = 0; j < L; ++j)
+            dma16(src + rowoff[j], __builtin_amdgcn_readfirstlane(dst + (uint32_t)((4 * j + wave) * 1024)));
     };
-    auto store_stage = [&](int buf, int tb) {
-        uint8_t *sm = smem + buf * STB;
-        const bool tail = tb == n_tb - 1 && tv < TB;
+    // Zero spectra >= tv of the landed last time block.
+    auto fix_tail = [&](int t) {
+        uint8_t *sm = smem + (t & 1) * STG;
+        for (int q = tid; q < STG / 16; q += kXThreads) {
+            const int bo = q * 16, r = (bo % OPB) / RB, c = ((bo % RB) / 16) ^ swz(r);
+            const int first = ((c % CPP) * 16) / ES;     // spectrum index of the chunk's first element
+            if (first + 16 / ES <= tv) continue;
+            uint32_t *wd = reinterpret_cast<uint32_t *>(sm + bo);
 #pragma unroll
-        for (int o = 0; o < 2; ++o)
+            for (int d = 0; d < 4; ++d) {
+                uint32_t msk = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = tid + kXThreads * u;
-                const int row = c >> 3, col = c & 7;
-                uint4 v = st[U * o + u];
-                if ((o ? J0 : I0) + row >= N) v = make_uint4(0, 0, 0, 0);
-                if (tail) {
-                    // zero the spectra past the valid count in the last time block
-                    const int off = (col & 3) * 16;
-                    uint32_t *wd = reinterpret_cast<uint32_t *>(&v);
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        uint32_t msk = 0;
-#pragma unroll
-                        for (int bb = 0; bb < 4; ++bb)
-                            if ((off + 4 * d + bb) / ES < tv) msk |= 0xffu << (8 * bb);
-                        wd[d] &= msk;
-                    }
-                }
-                *reinterpret_cast<uint4 *>(sm + o * OPB + row * kRowStride + col * 16) = v;
+                for (int bb = 0; bb < 4; ++bb)
+                    if (first + (4 * d + bb) / ES < tv) msk |= 0xffu << (8 * bb);
+                wd[d] &= msk;
             }
+        }
     };
+
+    // The lane's fragment chunk offsets within a row (the rows of a fragment
+    // read are m modulo 32, and swz depends on r mod 16 only).
+    int off[2][NT];
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) off[pl][t] = 16 * ((pl * CPP + h * NT + t) ^ swz(m));
 
     Acc re[FS][FS], im[FS][FS];
 #pragma unroll
@@ -253,25 +319,29 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
             }
         }
 
-    load_stage(0);
-    store_stage(0, 0);
-    __syncthreads();
-    for (int tb = 0; tb < n_tb; ++tb) {
-        const bool more = tb + 1 < n_tb;
-        if (more) load_stage(tb + 1);
-        if (active) {
-            const uint8_t *sI = smem + (tb & 1) * STB;
-            const uint8_t *sJ = sI + OPB;
-            const uint8_t *pa = sI + (wi * QS + m) * kRowStride + h * 32;
-            const uint8_t *pb = sJ + (wj * QS + m) * kRowStride + h * 32;
-            // one uniform branch per block keeps the MFMA stream branch-free
-            if (dwave)
-                wave_block<PREC, FS, true>(re, im, pa, pb);
-            else
-                wave_block<PREC, FS, false>(re, im, pa, pb);
+    const uint8_t *pa0 = smem + (wi * QS + m) * RB;
+    const uint8_t *pb0 = smem + OPB + (wj * QS + m) * RB;
+    const bool tail = tv < TB;
+
+    issue(0);
+    Frags<PREC, FS, NT> cur;
+    for (int t = 0; t < S; ++t) {
+        wait_vm<0>();                                   // this wave's copies of block t landed
+        __syncthreads();                                // block t landed; the other slot is free
+        if (t + 1 < S) issue(t + 1);
+        if (tail && t == S - 1) {
+            fix_tail(t);
+            __syncthreads();
         }
-        if (more) store_stage((tb + 1) & 1, tb + 1);
-        __syncthreads();
+        if (active) {
+            const int so = (t & 1) * STG;
+            cur.load(pa0 + so, pb0 + so, off);
+            // one uniform branch per stage keeps the MFMA stream branch-free
+            if (dwave)
+                wave_mfma<PREC, FS, NT, true>(re, im, cur);
+            else
+                wave_mfma<PREC, FS, NT, false>(re, im, cur);
+        }
     }
     if (!active) return;
 
@@ -336,7 +406,7 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
     int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, int64_t B,
     int first_call) {
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * stage_bytes(TILE)];
+    __shared__ __attribute__((aligned(16))) uint8_t smem[ring_bytes(TILE)];
     const int per = (n_work + 7) / 8;
     const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (w >= n_work) return;
@@ -360,7 +430,7 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
 template <int PREC, int TILE>
 __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(TILE == 64 ? 4 : 2))) void xengine_batched_kernel(
     const XQueue *__restrict__ plan, const XDesc *__restrict__ all_desc, unsigned int *__restrict__ counter) {
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * stage_bytes(TILE)];
+    __shared__ __attribute__((aligned(16))) uint8_t smem[ring_bytes(TILE)];
     __shared__ unsigned int s_item;
     const int tid = threadIdx.x;
     const int n_desc = plan->n_desc;
