@@ -15,6 +15,16 @@ Also reported on one JSON line:
                   the correlator's stream, against the MFMA peak of its type;
   forms        -- the same step in the FP16, int8 and FP8 forms, with X-engine
                   speed-ups over FP32;
+  equal_accuracy -- the same int8-valued spectra through the FP32, FP16 and
+                  int8 X-engines: every value is exact in all three element
+                  types, so the int8 result is the exact sum and the float
+                  forms differ from it by accumulation rounding only;
+  xengine_shapes -- X-engine alone at the larger array shapes (512 inputs x
+                  2048 channels x 2048 spectra for int8 / FP16, 1024 inputs x
+                  4096 channels x 1024 spectra for FP8 / FP32), against each
+                  type's MFMA peak;
+  batched      -- 64 uneven sub-arrays: persistent batched X-engine vs
+                  per-array launches, and the graph-replayed step;
   cpu_baseline -- the oracle (float64 direct DFT + triple-loop correlation)
                   timed on a bounded channel sample on the host cores, which
                   also gives each form's error against float64.
@@ -56,6 +66,9 @@ def parse():
     ap.add_argument("--batched-steps", type=int, default=8,
                     help="graph replays per integration in the batched section")
     ap.add_argument("--cpu-channels", type=int, default=768)
+    ap.add_argument("--no-equal-accuracy", action="store_true")
+    ap.add_argument("--no-shapes", action="store_true",
+                    help="skip the X-engine timings at the 512- and 1024-input shapes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "xengine_fp32_mwa-128x2-c1024_traffic.txt"),
@@ -144,6 +157,95 @@ def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     return c, out, inv, wall, ftimer.mean_ms(), xtimer.mean_ms()
+
+
+def int8_valued(torch, shape, seed):
+    """Seeded device spectra with int8 values: Gaussian, 16 LSB rms, clamped to
+    +-127 (the requantiser's default operating point)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    x = torch.randn(shape, generator=g, device="cuda", dtype=torch.float32) * 16.0
+    return x.round_().clamp_(-127, 127).to(torch.int8)
+
+
+def time_x(torch, c, A, reps):
+    """Mean X-engine time on held spectra, first call of an integration each
+    time (the accumulators are reset by a device dump in between, untimed)."""
+    dst = c.new_visibilities()
+    ts = []
+    for _ in range(reps):
+        c.dump(dst, reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.xengine(A)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return dst, sum(ts) / len(ts)
+
+
+def run_equal_accuracy(torch, corr, w, reps=5):
+    """Same int8-valued spectra into the FP32, FP16 and int8 X-engines."""
+    N, C, A = w.n_inputs, w.n_channels, w.n_integrate
+    S8 = int8_valued(torch, (A, C, N, 2), seed=7)
+    cm = N * (N + 1) // 2 * C * A
+    out, vis = {}, {}
+    for prec in ("int8", "fp16", "fp32"):
+        S = S8 if prec == "int8" else S8.to(corr.SPECTRA_DTYPE[corr.PRECISIONS[prec]])
+        c = corr.Correlator(w.n_stations, w.n_pols, C, A, prec)
+        c.xengine(A, S)                                # ingest the caller spectra
+        del S
+        v, ms = time_x(torch, c, A, reps)
+        c.xengine(A)
+        c.dump(v, reset=True)
+        vis[prec] = v.to(torch.float64)
+        c.close()
+        out[prec] = {"xengine_ms": ms, "xengine_tcmacs": cm / (ms * 1e-3) / 1e12,
+                     "mfma_frac": 8 * cm / (ms * 1e-3) / 1e12 / PEAK[prec]}
+    del S8
+    exact = vis["int8"][..., 0] + 1j * vis["int8"][..., 1]    # [C, B]
+    d = exact.real[:, torch.tensor([i * (i + 1) // 2 + i for i in range(N)], device=exact.device)]
+    il, jl = (torch.as_tensor(x, device=exact.device) for x in np.tril_indices(N))
+    norm = torch.sqrt(torch.clamp(d[:, il] * d[:, jl], min=1e-300))
+    for prec in ("fp16", "fp32"):
+        g = vis[prec][..., 0] + 1j * vis[prec][..., 1]
+        eF = torch.linalg.norm(g - exact, dim=1) / torch.linalg.norm(exact, dim=1)
+        en = torch.abs(g - exact) / norm
+        out[prec]["error_vs_exact"] = {"max_rel_frobenius": float(eF.max()), "max_normalised": float(en.max())}
+        out[prec]["speedup_vs_fp32"] = out["fp32"]["xengine_ms"] / out[prec]["xengine_ms"]
+    out["int8"]["error_vs_exact"] = {"max_rel_frobenius": 0.0, "max_normalised": 0.0}
+    out["int8"]["speedup_vs_fp32"] = out["fp32"]["xengine_ms"] / out["int8"]["xengine_ms"]
+    out["fp32"]["speedup_vs_fp32"] = 1.0
+    del vis, exact, d, norm
+    torch.cuda.empty_cache()
+    return {"workload": f"{w.name}: int8-valued spectra (16 LSB rms) shared by all three forms", **out}
+
+
+def run_shapes(torch, corr, reps=3):
+    """X-engine alone at the 512- and 1024-input shapes, int8-valued spectra."""
+    res = {}
+    for name, prec, st, C, A in (("512x2048x2048", "int8", 256, 2048, 2048),
+                                 ("512x2048x2048", "fp16", 256, 2048, 2048),
+                                 ("1024x4096x1024", "fp8", 512, 4096, 1024),
+                                 ("1024x4096x1024", "fp32", 512, 4096, 1024)):
+        N = 2 * st
+        S = int8_valued(torch, (A, C, N, 2), seed=11)
+        if prec != "int8":
+            S = S.to(corr.SPECTRA_DTYPE[corr.PRECISIONS[prec]])
+        c = corr.Correlator(st, 2, C, A, prec)
+        c.xengine(A, S)
+        del S
+        torch.cuda.empty_cache()
+        dst, ms = time_x(torch, c, A, reps)
+        del dst
+        cm = N * (N + 1) // 2 * C * A
+        tc = cm / (ms * 1e-3) / 1e12
+        res[f"{prec}/{name}"] = {"inputs": N, "channels": C, "spectra": A, "xengine_ms": ms,
+                                 "xengine_tcmacs": tc, "mfma_frac": 8 * tc / PEAK[prec]}
+        log(f"shape {name} {prec}: X {ms:.3f} ms, {tc:.1f} TCMAC/s, {100 * 8 * tc / PEAK[prec]:.1f}% of MFMA peak")
+        c.close()
+        torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(torch, oracle, synth, w, volts, results, n_chan):
@@ -328,6 +430,14 @@ def main():
                      "step_tcmacs": cmacs / wall_f / 1e12}
         log(f"{fp}: step {wall_f * 1e3:.3f} ms, F {f_ms_f:.3f} ms, X {x_ms_f:.3f} ms")
 
+    equal = None
+    if not args.no_equal_accuracy:
+        equal = run_equal_accuracy(torch, corr, w)
+        log("equal accuracy: X " + ", ".join(f"{p} {equal[p]['xengine_ms']:.3f} ms" for p in ("fp32", "fp16", "int8")))
+    shapes = None
+    if not args.no_shapes:
+        shapes = run_shapes(torch, corr)
+
     batched = None
     if not args.no_batched:
         log("batched: 64 uneven sub-arrays")
@@ -368,6 +478,8 @@ def main():
         "fengine_hbm_gbs": (N * A * C * (8 + 2 * ELEM_BYTES[prec])) / (f_ms * 1e-3) / 1e9,
         "roofline": roofline,
         "forms": forms,
+        "equal_accuracy": equal,
+        "xengine_shapes": shapes,
         "batched": batched,
         "cpu_baseline": cpu,
     }

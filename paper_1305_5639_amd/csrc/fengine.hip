@@ -239,7 +239,7 @@ template <> struct Bytes<16> { using T = uint4; };
 template <int C, int PREC>
 __global__ __launch_bounds__(kThreads) void fengine_kernel(
     const float2 *__restrict__ volts, int64_t ld, int N, int n_spectra, int n_valid_pad,
-    int groups_per_input, int n_work, const float *__restrict__ inv_scale,
+    int n_work, const float *__restrict__ inv_scale,
     const float2 *__restrict__ tw, uint8_t *__restrict__ spec, int n_tb_cap) {
     using E = typename Elem<PREC>::T;
     constexpr int T = kTC / C;                         // spectra per workgroup
@@ -257,11 +257,17 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(
     const int tid = threadIdx.x;
 
     // XCD-major work order: XCD x = blockIdx % 8 takes items [x*per, (x+1)*per).
+    // Items run input-fastest within a time block, GPT workgroups per (time
+    // block, input): the workgroups running together on an XCD then fill
+    // whole 128-byte lines (k, tb, p) of consecutive inputs, which merge in
+    // its L2 and leave it as contiguous runs.
+    constexpr int GPT = TB > T ? TB / T : 1;
     const int per = (n_work + 7) / 8;
     const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (w >= n_work) return;
-    const int p = w / groups_per_input;
-    const int a0 = (w % groups_per_input) * T;
+    const int rest = w / GPT;
+    const int p = rest % N;
+    const int a0 = ((rest / N) * GPT + w % GPT) * T;
 
     float2 v[kPerThread];
     fft<C, T>(v, lds, volts + (int64_t)p * ld, a0, n_spectra, tw, tid);
@@ -317,7 +323,7 @@ hipError_t launch_c(int N, const float2 *volts, int64_t ld, int n_spectra, const
     if (n_work <= 0 || n_work > (int64_t)1 << 30) return hipErrorInvalidValue;
     const int grid = (int)((n_work + 7) / 8) * 8;
     hipLaunchKernelGGL((fengine_kernel<C, PREC>), dim3(grid), dim3(kThreads), 0, stream, volts, ld, N,
-                       n_spectra, n_valid_pad, groups, (int)n_work, inv_scale, tw,
+                       n_spectra, n_valid_pad, (int)n_work, inv_scale, tw,
                        static_cast<uint8_t *>(spec), n_tb_cap);
     return hipGetLastError();
 }
