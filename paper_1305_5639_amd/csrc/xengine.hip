@@ -54,7 +54,6 @@ typedef __attribute__((address_space(1))) const uint8_t gu8;
 typedef __attribute__((address_space(1))) const u32x4 gu4;
 typedef __attribute__((address_space(1))) const float gf32;
 
-constexpr int kXThreads = 256;
 // LDS ring.  A stage is one time block of the TILE rows of both operand
 // slabs: 128-byte rows (both planes), two slots.  Rows have no padding; the
 // 16-byte chunk c of row r sits in slot c ^ swz(r).  A 16-byte-per-lane LDS
@@ -154,55 +153,50 @@ template <int NT> struct XT<P_FP8, NT> {
     }
 };
 
-// A wave's fragments of one stage: for each of its FS row blocks (a) and FS
-// column blocks (b), one fragment per plane.  pa / pb point at the lane's row
-// in the stage; off[plane] are the lane's swizzled chunk offsets in a row.
-template <int PREC, int FS, int NT> struct Frags {
-    using X = XT<PREC, NT>;
-    typename X::Frag a[FS][2], b[FS][2];
-    __device__ __forceinline__ void load(const uint8_t *pa, const uint8_t *pb, const int (&off)[2][NT]) {
-        constexpr int RB = kRB;
-#pragma unroll
-        for (int g = 0; g < FS; ++g) {
-            b[g][0] = X::load(pb + g * 32 * RB, off[0]);
-            b[g][1] = X::load(pb + g * 32 * RB, off[1]);
-        }
-#pragma unroll
-        for (int f = 0; f < FS; ++f) {
-            a[f][0] = X::load(pa + f * 32 * RB, off[0]);
-            a[f][1] = X::load(pa + f * 32 * RB, off[1]);
-        }
-    }
+// Wave layout of a TILE x TILE block: 2 x WC waves, each owning QS = TILE / 2
+// rows (FR blocks of 32) and one 32-column block.  TILE = 128: 8 waves of
+// 64 x 32; TILE = 64: 4 waves of 32 x 32.  Narrow waves keep the complex
+// accumulators of a wave at 32 FR registers each for Re and Im, so four waves
+// share each SIMD: while some wait at a barrier or on LDS, others issue MFMAs.
+template <int TILE> struct WaveGrid {
+    static constexpr int WC = TILE / 32;               // waves across the columns
+    static constexpr int NW = 2 * WC;                  // waves
+    static constexpr int THREADS = 64 * NW;
+    static constexpr int FR = TILE / 64;               // 32-row blocks per wave
+    static constexpr int QS = TILE / 2;                // rows per wave
 };
 
-// The MFMAs of one stage of a wave's quarter (FS x FS blocks of 32x32; FS = 2
-// for 128-input tiles, 1 for 64-input tiles): NSUB MFMAs per fragment, four
-// real products per 32x32 block (Re += Ar Br + Ai Bi, Im += Ar Bi + Ai (-Br)),
-// issued across the column blocks so dependent MFMAs are apart.  SKIP_UPPER
-// (FS = 2 only): a diagonal wave leaves out its upper 32x32 block (rows 0-31,
-// columns 32-63).
-template <int PREC, int FS, int NT, bool SKIP_UPPER, typename Acc>
-__device__ __forceinline__ void wave_mfma(Acc (&re)[FS][FS], Acc (&im)[FS][FS], const Frags<PREC, FS, NT> &q) {
-    using X = XT<PREC, NT>;
-    typename X::Frag nb[FS];
+// One stage of a wave's FR blocks of 32x32.  pa / pb point at the lane's row
+// (row block 0) and column in the stage; off[plane][t] are the lane's
+// swizzled chunk offsets in a row.  Four real products per block (Re += Ar Br
+// + Ai Bi, Im += Ar Bi + Ai (-Br)).  The column fragment is read once, each
+// row block's fragments just before its MFMAs, and (except for FP8, whose
+// MFMA takes both chunks) one 16-byte chunk at a time, which keeps the live
+// fragment registers few enough for four waves per SIMD.  SKIP0: a diagonal
+// wave whose first row block lies wholly above the diagonal leaves it out.
+template <int PREC, int FR, bool SKIP0, typename Acc>
+__device__ __forceinline__ void wave_stage(Acc (&re)[FR], Acc (&im)[FR], const uint8_t *pa, const uint8_t *pb,
+                                           const int (&off)[2][kNT]) {
+    constexpr int NC = PREC == P_FP8 ? 1 : kNT;        // chunk groups per stage
+    constexpr int NTC = kNT / NC;                      // chunks per fragment
+    using X = XT<PREC, NTC>;
 #pragma unroll
-    for (int g = 0; g < FS; ++g) nb[g] = X::neg(q.b[g][0]);
+    for (int t = 0; t < NC; ++t) {
+        const typename X::Frag b0 = X::load(pb, off[0] + t * NTC);
+        const typename X::Frag b1 = X::load(pb, off[1] + t * NTC);
+        const typename X::Frag nb = X::neg(b0);
 #pragma unroll
-    for (int f = 0; f < FS; ++f) {
+        for (int f = 0; f < FR; ++f) {
+            if (SKIP0 && f == 0) continue;
+            const typename X::Frag a0 = X::load(pa + f * 32 * kRB, off[0] + t * NTC);
+            const typename X::Frag a1 = X::load(pa + f * 32 * kRB, off[1] + t * NTC);
 #pragma unroll
-        for (int e = 0; e < X::NSUB; ++e) {
-#pragma unroll
-            for (int g = 0; g < FS; ++g)
-                if (!(SKIP_UPPER && f < g)) X::mfma(re[f][g], q.a[f][0], q.b[g][0], e);    // + xr_i xr_j
-#pragma unroll
-            for (int g = 0; g < FS; ++g)
-                if (!(SKIP_UPPER && f < g)) X::mfma(im[f][g], q.a[f][0], q.b[g][1], e);    // + xr_i xi_j
-#pragma unroll
-            for (int g = 0; g < FS; ++g)
-                if (!(SKIP_UPPER && f < g)) X::mfma(re[f][g], q.a[f][1], q.b[g][1], e);    // + xi_i xi_j
-#pragma unroll
-            for (int g = 0; g < FS; ++g)
-                if (!(SKIP_UPPER && f < g)) X::mfma(im[f][g], q.a[f][1], nb[g], e);        // - xi_i xr_j
+            for (int e = 0; e < X::NSUB; ++e) {
+                X::mfma(re[f], a0, b0, e);             // + xr_i xr_j
+                X::mfma(im[f], a0, b1, e);             // + xr_i xi_j
+                X::mfma(re[f], a1, b1, e);             // + xi_i xi_j
+                X::mfma(im[f], a1, nb, e);             // - xi_i xr_j
+            }
         }
     }
 }
@@ -229,7 +223,7 @@ template <int n> __device__ __forceinline__ void wait_vm() {
 }
 
 // The whole K loop and epilogue of one TILE x TILE block of channel k, rows
-// I0.., columns J0..; 4 waves, each owning a (TILE/2) x (TILE/2) quarter.
+// I0.., columns J0.., by the waves of WaveGrid<TILE>.
 // Time blocks stream through a two-slot LDS ring by direct global-to-LDS
 // copies: the copy of time block t + 1 is issued when block t starts and
 // lands while its MFMAs run.  The copies bypass registers, so the block
@@ -246,27 +240,29 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     using Acc = typename XT<PREC, NT>::Acc;
     constexpr int ES = PREC == P_FP32 ? 4 : (PREC == P_FP16 ? 2 : 1);
     constexpr int TB = kRowBytes / ES;
-    constexpr int QS = TILE / 2;                        // rows of a wave's quarter
-    constexpr int FS = QS / 32;                         // 32x32 blocks per quarter side
+    using G = WaveGrid<TILE>;
+    constexpr int QS = G::QS, FR = G::FR, WC = G::WC, NW = G::NW, THREADS = G::THREADS;
     constexpr int OPB = TILE * RB;                      // one operand slab of a stage
     constexpr int STG = 2 * OPB;                        // one stage
-    constexpr int L = STG / (4 * 1024);                 // 1 KB copies per wave per stage
+    constexpr int L = STG / (NW * 1024);                // 1 KB copies per wave per stage
     static_assert(2 * STG == ring_bytes(TILE) && L < 64, "ring geometry");
     const int wave = tid >> 6, lane = tid & 63;
-    const int wi = wave >> 1, wj = wave & 1;
+    const int wi = wave / WC, wj = wave % WC;
     const int m = lane & 31, h = lane >> 5;
     const bool diag = I0 == J0;
-    const bool active = !(diag && wj > wi);
-    const bool dwave = FS > 1 && diag && wi == wj;      // skip the upper 32x32 block
+    // on a diagonal block, a wave whose columns all lie right of its rows
+    // idles; one whose first 32 rows do skips that row block
+    const bool active = !(diag && 32 * wj > wi * QS + QS - 1);
+    const bool dwave = FR > 1 && diag && 32 * wj > wi * QS + 31;
     const int S = n_tb;                                 // stages
 
-    // Copy j of this wave covers stage bytes [g KB, (g + 1) KB), g = 4 j + wave;
+    // Copy j of this wave covers stage bytes [g KB, (g + 1) KB), g = NW j + wave;
     // lane l writes bytes 16 l of it: slab o, row r, slot sl, which holds
     // chunk c = sl ^ swz(r), i.e. bytes [16 (c % CPP), +16) of plane c / CPP.
     int rowoff[L];
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-        const int bo = (4 * j + wave) * 1024 + 16 * lane;
+        const int bo = (NW * j + wave) * 1024 + 16 * lane;
         const int o = bo / OPB, r = (bo % OPB) / RB, c = ((bo % RB) / 16) ^ swz(r);
         const int pr = min((o ? J0 : I0) + r, N - 1);
         rowoff[j] = pr * RB + (c / CPP) * kRowBytes + (c % CPP) * 16;
@@ -278,12 +274,12 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
         const uint32_t dst = lds0 + (uint32_t)((t & 1) * STG);
 #pragma unroll
         for (int j = 0; j < L; ++j)
-            dma16(src + rowoff[j], __builtin_amdgcn_readfirstlane(dst + (uint32_t)((4 * j + wave) * 1024)));
+            dma16(src + rowoff[j], __builtin_amdgcn_readfirstlane(dst + (uint32_t)((NW * j + wave) * 1024)));
     };
     // Zero spectra >= tv of the landed last time block.
     auto fix_tail = [&](int t) {
         uint8_t *sm = smem + (t & 1) * STG;
-        for (int q = tid; q < STG / 16; q += kXThreads) {
+        for (int q = tid; q < STG / 16; q += THREADS) {
             const int bo = q * 16, r = (bo % OPB) / RB, c = ((bo % RB) / 16) ^ swz(r);
             const int first = ((c % CPP) * 16) / ES;     // spectrum index of the chunk's first element
             if (first + 16 / ES <= tv) continue;
@@ -307,24 +303,20 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
 #pragma unroll
         for (int t = 0; t < NT; ++t) off[pl][t] = 16 * ((pl * CPP + h * NT + t) ^ swz(m));
 
-    Acc re[FS][FS], im[FS][FS];
+    Acc re[FR], im[FR];
 #pragma unroll
-    for (int f = 0; f < FS; ++f)
+    for (int f = 0; f < FR; ++f)
 #pragma unroll
-        for (int g = 0; g < FS; ++g) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                re[f][g][r] = 0;
-                im[f][g][r] = 0;
-            }
+        for (int r = 0; r < 16; ++r) {
+            re[f][r] = 0;
+            im[f][r] = 0;
         }
 
     const uint8_t *pa0 = smem + (wi * QS + m) * RB;
-    const uint8_t *pb0 = smem + OPB + (wj * QS + m) * RB;
+    const uint8_t *pb0 = smem + OPB + (wj * 32 + m) * RB;
     const bool tail = tv < TB;
 
     issue(0);
-    Frags<PREC, FS, NT> cur;
     for (int t = 0; t < S; ++t) {
         wait_vm<0>();                                   // this wave's copies of block t landed
         __syncthreads();                                // block t landed; the other slot is free
@@ -335,60 +327,64 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
         }
         if (active) {
             const int so = (t & 1) * STG;
-            cur.load(pa0 + so, pb0 + so, off);
             // one uniform branch per stage keeps the MFMA stream branch-free
             if (dwave)
-                wave_mfma<PREC, FS, NT, true>(re, im, cur);
+                wave_stage<PREC, FR, true>(re, im, pa0 + so, pb0 + so, off);
             else
-                wave_mfma<PREC, FS, NT, false>(re, im, cur);
+                wave_stage<PREC, FR, false>(re, im, pa0 + so, pb0 + so, off);
         }
     }
     if (!active) return;
 
     // Epilogue: element r of a 32x32 block is (row 8(r/4) + 4h + r%4, column m).
-    // All of a block's accumulator reads are issued before any write; elements
-    // outside the triangle or past N read a valid address and are not written.
+    // Rows go in two halves of 8; each half's accumulator reads are issued
+    // before any of its writes.  Elements outside the triangle or past N read a
+    // valid address and are not written.  Offsets within a channel fit 32 bits
+    // (N(N+1)/2 < 2^31 for N <= 8192).
     using E = typename std::conditional<PREC == P_INT8, int, float>::type;
     typedef E T2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(1))) T2 gT2;
     gT2 *out = (gT2 *)acc_out + (int64_t)k * B;
     const float s2 = (PREC != P_INT8 && scale2) ? ((gf32 *)scale2)[k] : 1.0f;
+    const int j = J0 + wj * 32 + m;
 #pragma unroll
-    for (int f = 0; f < FS; ++f)
+    for (int f = 0; f < FR; ++f) {
+        if (dwave && f == 0) continue;
 #pragma unroll
-        for (int g = 0; g < FS; ++g) {
-            if (dwave && f < g) continue;
-            const int j = J0 + wj * QS + g * 32 + m;
-            int64_t idx[16];
+        for (int hh = 0; hh < 2; ++hh) {
+            int idx[8];
             uint32_t ok = 0;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int q = 0; q < 8; ++q) {
+                const int r = 8 * hh + q;
                 const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 const bool in = i < N && j <= i;
-                ok |= (uint32_t)in << r;
-                idx[r] = in ? (int64_t)i * (i + 1) / 2 + j : 0;
+                ok |= (uint32_t)in << q;
+                idx[q] = in ? i * (i + 1) / 2 + j : 0;
             }
-            T2 old[16];
+            T2 old[8];
             if (!first_call) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) old[r] = out[idx[r]];
+                for (int q = 0; q < 8; ++q) old[q] = out[idx[q]];
             }
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int q = 0; q < 8; ++q) {
+                const int r = 8 * hh + q;
                 const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 T2 v;
                 if constexpr (PREC == P_INT8) {
-                    v = T2{re[f][g][r], i == j ? 0 : im[f][g][r]};
+                    v = T2{re[f][r], i == j ? 0 : im[f][r]};
                 } else {
-                    v = T2{re[f][g][r] * s2, i == j ? 0.0f : im[f][g][r] * s2};
+                    v = T2{re[f][r] * s2, i == j ? 0.0f : im[f][r] * s2};
                 }
                 if (!first_call) {
-                    v.x += old[r].x;
-                    v.y += old[r].y;
+                    v.x += old[q].x;
+                    v.y += old[q].y;
                 }
-                if ((ok >> r) & 1u) out[idx[r]] = v;
+                if ((ok >> q) & 1u) out[idx[q]] = v;
             }
         }
+    }
 }
 
 // Lower-triangle block t of a tiling with blocks (bi, bj), bj <= bi, in the
@@ -402,7 +398,7 @@ __device__ __forceinline__ void tri_block(int t, int &bi, int &bj) {
 }
 
 template <int PREC, int TILE>
-__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) void xengine_kernel(
+__global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(4))) void xengine_kernel(
     const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
     int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, int64_t B,
     int first_call) {
@@ -428,7 +424,7 @@ __global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(2))) 
 // descriptors follow their sorted order (largest item first) and a workgroup
 // finds its descriptor by binary search over the queue offsets.
 template <int PREC, int TILE>
-__global__ __launch_bounds__(kXThreads) __attribute__((amdgpu_waves_per_eu(TILE == 64 ? 4 : 2))) void xengine_batched_kernel(
+__global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(4))) void xengine_batched_kernel(
     const XQueue *__restrict__ plan, const XDesc *__restrict__ all_desc, unsigned int *__restrict__ counter) {
     __shared__ __attribute__((aligned(16))) uint8_t smem[ring_bytes(TILE)];
     __shared__ unsigned int s_item;
@@ -490,7 +486,7 @@ hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec,
     const int grid = (int)((n_work + 7) / 8) * 8;
     const int64_t k_stride = channel_stride(n_tb_cap, N);
     const int64_t B = (int64_t)N * (N + 1) / 2;
-    hipLaunchKernelGGL((xengine_kernel<PREC, TILE>), dim3(grid), dim3(kXThreads), 0, stream,
+    hipLaunchKernelGGL((xengine_kernel<PREC, TILE>), dim3(grid), dim3(WaveGrid<TILE>::THREADS), 0, stream,
                        static_cast<const uint8_t *>(spec), N, n_tiles, (int)n_work, n_tb, tv, k_stride,
                        scale2, acc, B, first_call);
     return hipGetLastError();
@@ -520,7 +516,7 @@ hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n
 template <int PREC, int TILE>
 hipError_t launch_batched_t(const XQueue *d_plan, const XDesc *d_desc, unsigned int *counter, int grid,
                             hipStream_t stream) {
-    hipLaunchKernelGGL((xengine_batched_kernel<PREC, TILE>), dim3(grid), dim3(kXThreads), 0, stream, d_plan, d_desc,
+    hipLaunchKernelGGL((xengine_batched_kernel<PREC, TILE>), dim3(grid), dim3(WaveGrid<TILE>::THREADS), 0, stream, d_plan, d_desc,
                        counter);
     return hipGetLastError();
 }
