@@ -120,81 +120,133 @@ __device__ __forceinline__ void bfly_index(int b, int &t, int &j) {
     }
 }
 
-// One Stockham pass of radix R after NS points have been combined: butterfly
-// (t, j) takes x[t][j + r C/R], multiplies element r by W_C^(r (j mod NS) C/(NS R)),
-// does an R-point DFT and (unless LAST) writes x[t][(j/NS) NS R + j mod NS + r NS].
-template <int C, int T, int R, int NS, bool FIRST, bool LAST>
-__device__ __forceinline__ void fft_pass(float2 *v, float2 *lds, const float2 *__restrict__ src, int a0,
-                                         int n_spectra, const float2 *__restrict__ tw, int tid) {
+// LDS index of element i of spectrum t (rows padded as Plan<C> says).
+template <int C>
+__device__ __forceinline__ int lidx(int t, int i) {
     using P = Plan<C>;
-    constexpr int CP = C + (C >> P::SH) + P::EX;
+    return t * (C + (C >> P::SH) + P::EX) + i + (i >> P::SH);
+}
+
+// First Stockham pass, radix R: butterfly (t, j) takes x[t][j + r C/R] straight
+// from global memory (spectra past n_spectra read as zero) and does an R-point
+// DFT; no twiddles precede the first pass.
+template <int C, int T, int R>
+__device__ __forceinline__ void first_pass(float2 *v, const float2 *__restrict__ src, int a0, int n_spectra,
+                                           int tid) {
+    constexpr int Q = kPerThread / R, CR = C / R;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        int t, j;
+        bfly_index<C, T, R, false>(tid + kThreads * q, t, j);
+        float2 *x = v + q * R;
+        const bool ok = (a0 + t) < n_spectra;
+        const float2 *row = src + (int64_t)(a0 + t) * C + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = ok ? row[r * CR] : make_float2(0.f, 0.f);
+        Dft<R>::run(x);
+    }
+}
+
+// A later pass of radix R after NS points have been combined: butterfly (t, j)
+// (already holding x[t][j + r C/R]) multiplies element r by
+// W_C^(r (j mod NS) C/(NS R)) and does an R-point DFT.
+template <int C, int T, int R, int NS, bool REMAP>
+__device__ __forceinline__ void later_pass(float2 *v, const float2 *__restrict__ tw, int tid) {
     constexpr int Q = kPerThread / R;
-    constexpr int CR = C / R;
-    constexpr bool REMAP = LAST && !FIRST;
-    if constexpr (!FIRST) __syncthreads();             // the previous pass's stores are visible
+    constexpr int LR = ilog2(R);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int t, j;
         bfly_index<C, T, R, REMAP>(tid + kThreads * q, t, j);
         float2 *x = v + q * R;
-        if constexpr (FIRST) {
-            const bool ok = (a0 + t) < n_spectra;
-            const float2 *row = src + (int64_t)(a0 + t) * C + j;
+        const int m = (j % NS) * (C / (NS * R));
+        float2 wp[LR];                                 // W^(m 2^i)
 #pragma unroll
-            for (int r = 0; r < R; ++r) x[r] = ok ? row[r * CR] : make_float2(0.f, 0.f);
-        } else {
+        for (int i = 0; i < LR; ++i) wp[i] = tw[m << i];
+        float2 w[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = j + r * CR;
-                x[r] = lds[t * CP + i + (i >> P::SH)];
-            }
-        }
-        if constexpr (NS > 1) {
-            constexpr int LR = ilog2(R);
-            const int m = (j % NS) * (C / (NS * R));
-            float2 wp[LR];                             // W^(m 2^i)
-#pragma unroll
-            for (int i = 0; i < LR; ++i) wp[i] = tw[m << i];
-            float2 w[R];
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                const int hb = 31 - __builtin_clz(r);
-                w[r] = (r == (1 << hb)) ? wp[hb] : cmul(w[r - (1 << hb)], wp[hb]);
-                x[r] = cmul(x[r], w[r]);
-            }
+        for (int r = 1; r < R; ++r) {
+            const int hb = 31 - __builtin_clz(r);
+            w[r] = (r == (1 << hb)) ? wp[hb] : cmul(w[r - (1 << hb)], wp[hb]);
+            x[r] = cmul(x[r], w[r]);
         }
         Dft<R>::run(x);
     }
-    if constexpr (!LAST) {
-        if constexpr (!FIRST) __syncthreads();         // every thread has read this pass's inputs
+}
+
+// Stockham reordering between a pass (radix R1 after NS1 points) and the next
+// (radix R2): butterfly (t, j) of the first writes element r to
+// x[t][(j/NS1) NS1 R1 + j mod NS1 + r NS1], butterfly (t', j') of the next
+// reads x[t'][j' + r C/R2].  SPLIT: the LDS holds one float per element, so
+// the real parts go first and the imaginary parts second, each component read
+// back taking the registers of one just written (half the LDS, so more
+// workgroups per CU); otherwise whole complex values in one round.
+// wait_first: the LDS may still be read by an earlier exchange.
+template <int C, int T, int R1, int NS1, int R2, bool REMAP2, bool SPLIT>
+__device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wait_first) {
+    constexpr int Q1 = kPerThread / R1, Q2 = kPerThread / R2, CR2 = C / R2;
+    if constexpr (!SPLIT) {
+        float2 *l2 = reinterpret_cast<float2 *>(lds);
+        if (wait_first) __syncthreads();
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < Q1; ++q) {
             int t, j;
-            bfly_index<C, T, R, false>(tid + kThreads * q, t, j);
-            const int base = (j / NS) * NS * R + (j % NS);
+            bfly_index<C, T, R1, false>(tid + kThreads * q, t, j);
+            const int base = (j / NS1) * NS1 * R1 + (j % NS1);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = base + r * NS;
-                lds[t * CP + i + (i >> P::SH)] = v[q * R + r];
+            for (int r = 0; r < R1; ++r) l2[lidx<C>(t, base + r * NS1)] = v[q * R1 + r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q2; ++q) {
+            int t, j;
+            bfly_index<C, T, R2, REMAP2>(tid + kThreads * q, t, j);
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[q * R2 + r] = l2[lidx<C>(t, j + r * CR2)];
+        }
+        return;
+    }
+    float xr[kPerThread];
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        if (comp == 1 || wait_first) __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q1; ++q) {
+            int t, j;
+            bfly_index<C, T, R1, false>(tid + kThreads * q, t, j);
+            const int base = (j / NS1) * NS1 * R1 + (j % NS1);
+#pragma unroll
+            for (int r = 0; r < R1; ++r) lds[lidx<C>(t, base + r * NS1)] = comp ? v[q * R1 + r].y : v[q * R1 + r].x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q2; ++q) {
+            int t, j;
+            bfly_index<C, T, R2, REMAP2>(tid + kThreads * q, t, j);
+#pragma unroll
+            for (int r = 0; r < R2; ++r) {
+                const float e = lds[lidx<C>(t, j + r * CR2)];
+                if (comp == 0) xr[q * R2 + r] = e;
+                else v[q * R2 + r] = make_float2(xr[q * R2 + r], e);
             }
         }
     }
 }
 
 // The passes of Plan<C>; v ends with the last pass's outputs in registers.
-template <int C, int T>
-__device__ __forceinline__ void fft(float2 *v, float2 *lds, const float2 *__restrict__ src, int a0, int n_spectra,
+template <int C, int T, bool SPLIT>
+__device__ __forceinline__ void fft(float2 *v, float *lds, const float2 *__restrict__ src, int a0, int n_spectra,
                                     const float2 *__restrict__ tw, int tid) {
     using P = Plan<C>;
-    if constexpr (P::NP == 1) {
-        fft_pass<C, T, P::R0, 1, true, true>(v, lds, src, a0, n_spectra, tw, tid);
-    } else if constexpr (P::NP == 2) {
-        fft_pass<C, T, P::R0, 1, true, false>(v, lds, src, a0, n_spectra, tw, tid);
-        fft_pass<C, T, P::R1, P::R0, false, true>(v, lds, src, a0, n_spectra, tw, tid);
-    } else {
-        fft_pass<C, T, P::R0, 1, true, false>(v, lds, src, a0, n_spectra, tw, tid);
-        fft_pass<C, T, P::R1, P::R0, false, false>(v, lds, src, a0, n_spectra, tw, tid);
-        fft_pass<C, T, P::R2, P::R0 * P::R1, false, true>(v, lds, src, a0, n_spectra, tw, tid);
+    first_pass<C, T, P::R0>(v, src, a0, n_spectra, tid);
+    if constexpr (P::NP == 2) {
+        exchange<C, T, P::R0, 1, P::R1, true, SPLIT>(v, lds, tid, false);
+        later_pass<C, T, P::R1, P::R0, true>(v, tw, tid);
+    } else if constexpr (P::NP == 3) {
+        exchange<C, T, P::R0, 1, P::R1, false, SPLIT>(v, lds, tid, false);
+        later_pass<C, T, P::R1, P::R0, false>(v, tw, tid);
+        exchange<C, T, P::R1, P::R0, P::R2, true, SPLIT>(v, lds, tid, true);
+        later_pass<C, T, P::R2, P::R0 * P::R1, true>(v, tw, tid);
     }
 }
 
@@ -237,7 +289,7 @@ template <> struct Bytes<8> { using T = uint2; };
 template <> struct Bytes<16> { using T = uint4; };
 
 template <int C, int PREC>
-__global__ __launch_bounds__(kThreads) void fengine_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC == P_FP32 ? 2 : 3))) void fengine_kernel(
     const float2 *__restrict__ volts, int64_t ld, int N, int n_spectra, int n_valid_pad,
     int n_work, const float *__restrict__ inv_scale,
     const float2 *__restrict__ tw, uint8_t *__restrict__ spec, int n_tb_cap) {
@@ -246,14 +298,22 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(
     using P = Plan<C>;
     static_assert(P::R0 * P::R1 * P::R2 == C, "radix plan must multiply to C");
     constexpr int RL = P::NP == 1 ? P::R0 : (P::NP == 2 ? P::R1 : P::R2);   // last radix
-    constexpr int CP = C + (C >> P::SH) + P::EX;       // LDS row stride (float2)
+    constexpr int CP = C + (C >> P::SH) + P::EX;       // LDS row stride (floats)
     constexpr int ES = (int)sizeof(E);
     constexpr int TB = kRowBytes / ES;                 // spectra per time block
     constexpr int S = T * ES;                          // bytes of one staged row
     constexpr int CH = S < 16 ? S : 16;                // store chunk
-    static_assert(2 * C * S <= T * CP * 8, "staging must fit the FFT buffer");
+    // The low-precision forms keep one float per element in LDS: the FFT's
+    // reorderings move one component at a time, which halves the buffer so
+    // three workgroups share a CU.  FP32, whose wider output staging needs the
+    // registers that would allow that, keeps whole complex values (two
+    // workgroups per CU, one round per reordering).
+    constexpr bool SPLIT = PREC != P_FP32;
+    constexpr int LF = SPLIT ? 1 : 2;                  // floats per LDS element
+    constexpr int NPL = 2 * C * S <= T * CP * 4 * LF ? 2 : 1;   // planes staged at a time
+    static_assert(NPL * C * S <= T * CP * 4 * LF, "staging must fit the FFT buffer");
 
-    __shared__ __attribute__((aligned(16))) float2 lds[T * CP];
+    __shared__ __attribute__((aligned(16))) float lds[T * CP * LF];
     const int tid = threadIdx.x;
 
     // XCD-major work order: XCD x = blockIdx % 8 takes items [x*per, (x+1)*per).
@@ -270,44 +330,48 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(
     const int a0 = ((rest / N) * GPT + w % GPT) * T;
 
     float2 v[kPerThread];
-    fft<C, T>(v, lds, volts + (int64_t)p * ld, a0, n_spectra, tw, tid);
+    fft<C, T, SPLIT>(v, lds, volts + (int64_t)p * ld, a0, n_spectra, tw, tid);
 
     // v[q RL + r] holds channel k = j + r C/RL of spectrum t for last-pass
-    // butterfly b = tid + 256 q, (t, j) = (b % T, b / T).
-    constexpr int CR = C / RL;
-    __syncthreads();                                   // every thread is done reading lds
-    uint8_t *stage = reinterpret_cast<uint8_t *>(lds); // [plane][k][T] elements
-#pragma unroll
-    for (int q = 0; q < kPerThread / RL; ++q) {
-        const int b = tid + kThreads * q;
-        const int t = b % T, j = b / T;
-#pragma unroll
-        for (int r = 0; r < RL; ++r) {
-            const int k = j + r * CR;
-            const float s = inv_scale ? inv_scale[k] : 1.0f;
-            const float2 y = v[q * RL + r];
-            *reinterpret_cast<E *>(stage + (0 * C + k) * S + t * ES) = Elem<PREC>::conv(y.x * s);
-            *reinterpret_cast<E *>(stage + (1 * C + k) * S + t * ES) = Elem<PREC>::conv(y.y * s);
-        }
-    }
-    __syncthreads();
-
-    // Store staged rows: chunk c covers bytes [c*CH, (c+1)*CH) of the stage,
-    // i.e. row = plane*C + k and spectra a0 + x*CH/ES ...
+    // butterfly b = tid + 256 q, (t, j) = (b % T, b / T).  NPL planes at a time
+    // are requantised and staged in LDS as [plane][channel][spectrum], then
+    // stored as runs of consecutive spectra of each (channel, plane) row.
     // Destination: spec[k][tb][p][plane][TB].
+    constexpr int CR = C / RL;
     using V = typename Bytes<CH>::T;
     constexpr int CPR = S / CH;                        // chunks per staged row
-    constexpr int NCH = 2 * C * CPR;
+    constexpr int NCH = NPL * C * CPR;
     const int64_t k_stride = channel_stride(n_tb_cap, N);
-    for (int c = tid; c < NCH; c += kThreads) {
-        const int row = c / CPR, x = c % CPR;
-        const int pl = row / C, k = row % C;
-        const int a = a0 + x * (CH / ES);
-        if (a >= n_valid_pad) continue;
-        const int tb = a / TB, within = a % TB;
-        uint8_t *dst = spec + (int64_t)k * k_stride + ((int64_t)tb * N + p) * (2 * kRowBytes) +
-                       pl * kRowBytes + within * ES;
-        *reinterpret_cast<V *>(dst) = *reinterpret_cast<const V *>(stage + c * CH);
+    uint8_t *stage = reinterpret_cast<uint8_t *>(lds);
+#pragma unroll
+    for (int pl0 = 0; pl0 < 2; pl0 += NPL) {
+        __syncthreads();                               // every thread is done reading lds
+#pragma unroll
+        for (int q = 0; q < kPerThread / RL; ++q) {
+            const int b = tid + kThreads * q;
+            const int t = b % T, j = b / T;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int k = j + r * CR;
+                const float sc = inv_scale ? inv_scale[k] : 1.0f;
+                const float2 y = v[q * RL + r];
+#pragma unroll
+                for (int pp = 0; pp < NPL; ++pp)
+                    *reinterpret_cast<E *>(stage + (pp * C + k) * S + t * ES) =
+                        Elem<PREC>::conv((pl0 + pp ? y.y : y.x) * sc);
+            }
+        }
+        __syncthreads();
+        for (int c = tid; c < NCH; c += kThreads) {
+            const int row = c / CPR, x = c % CPR;
+            const int pl = pl0 + row / C, k = row % C;
+            const int a = a0 + x * (CH / ES);
+            if (a >= n_valid_pad) continue;
+            const int tb = a / TB, within = a % TB;
+            uint8_t *dst = spec + (int64_t)k * k_stride + ((int64_t)tb * N + p) * (2 * kRowBytes) +
+                           pl * kRowBytes + within * ES;
+            *reinterpret_cast<V *>(dst) = *reinterpret_cast<const V *>(stage + c * CH);
+        }
     }
 }
 
