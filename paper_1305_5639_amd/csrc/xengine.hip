@@ -337,7 +337,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     if (!active) return;
 
     // Epilogue: element r of a 32x32 block is (row 8(r/4) + 4h + r%4, column m).
-    // Rows go in two halves of 8; each half's accumulator reads are issued
+    // Rows go in batches of EH; each batch's accumulator reads are issued
     // before any of its writes.  Elements outside the triangle or past N read a
     // valid address and are not written.  Offsets within a channel fit 32 bits
     // (N(N+1)/2 < 2^31 for N <= 8192).
@@ -347,29 +347,32 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     gT2 *out = (gT2 *)acc_out + (int64_t)k * B;
     const float s2 = (PREC != P_INT8 && scale2) ? ((gf32 *)scale2)[k] : 1.0f;
     const int j = J0 + wj * 32 + m;
+    // rows of a block per batch of accumulator reads: all 16 where a wave has
+    // one row block, 8 where it has two (the registers allow no more)
+    constexpr int EH = FR == 1 ? 16 : 8;
 #pragma unroll
     for (int f = 0; f < FR; ++f) {
         if (dwave && f == 0) continue;
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            int idx[8];
+        for (int hh = 0; hh < 16 / EH; ++hh) {
+            int idx[EH];
             uint32_t ok = 0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int r = 8 * hh + q;
+            for (int q = 0; q < EH; ++q) {
+                const int r = EH * hh + q;
                 const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 const bool in = i < N && j <= i;
                 ok |= (uint32_t)in << q;
                 idx[q] = in ? i * (i + 1) / 2 + j : 0;
             }
-            T2 old[8];
+            T2 old[EH];
             if (!first_call) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) old[q] = out[idx[q]];
+                for (int q = 0; q < EH; ++q) old[q] = out[idx[q]];
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int r = 8 * hh + q;
+            for (int q = 0; q < EH; ++q) {
+                const int r = EH * hh + q;
                 const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 T2 v;
                 if constexpr (PREC == P_INT8) {
