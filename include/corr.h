@@ -213,17 +213,24 @@ CORR_API corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *ti
 
 /*
  * Batched form: many sub-arrays of uneven size (stations, channels,
- * integration) correlated by persistent X-engine launches -- one per block
- * size in use, so at most two -- that drain a work list of (sub-array,
- * channel, block) items, largest first.  All
- * sub-arrays share one precision and stream.  Each sub-array is an ordinary
- * handle owned by the batch (corr_batch_get): use corr_fengine,
- * corr_dump_visibilities and corr_autotune on it as usual; corr_destroy on it
- * is CORR_E_STATE.  Sub-array accumulators are zeroed at creation and a
- * dump with reset zeroes them right away (a kernel, not a memset), so a
- * sequence of corr_fengine / corr_xengine_batched calls can be captured into
- * a HIP graph once a first corr_xengine_batched call has been made outside
- * the capture.
+ * integration) correlated together.  As in the paper's space-division view
+ * of the correlation triangle (Section 4), each sub-array's triangle of
+ * pairs is cut into blocks; the (sub-array, channel, block) items of all
+ * sub-arrays are drained by persistent X-engine launches -- one per block
+ * size in use, so at most two -- from eight per-XCD work queues (channels
+ * split evenly, largest items first, idle workgroups take work from the
+ * other queues).  All sub-arrays share one precision and stream.  Each
+ * sub-array is an ordinary handle owned by the batch (corr_batch_get): use
+ * corr_fengine, corr_dump_visibilities and corr_autotune on it as usual;
+ * corr_destroy on it is CORR_E_STATE.  Sub-array accumulators are zeroed at
+ * creation and a dump with reset zeroes them right away (a kernel, not a
+ * memset), so a sequence of corr_fengine / corr_xengine_batched calls can be
+ * captured into a HIP graph once a first corr_xengine_batched call with the
+ * same n_spectra has been made outside the capture.  A changed work list
+ * during capture is CORR_E_STATE; after it changes outside a capture,
+ * capture again (an older graph then reads the new work plan, which stays
+ * within every sub-array's buffers, but launches only the block sizes it
+ * was captured with).
  */
 typedef struct corr_batch *corr_batch_handle;
 
