@@ -124,8 +124,15 @@ class Timer:
         e.record(self.torch.cuda.current_stream())
         self.pairs.append((s, e))
 
+    def times(self):
+        return [a.elapsed_time(b) for a, b in self.pairs]
+
     def mean_ms(self):
-        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs])) if self.pairs else float("nan")
+        return float(np.mean(self.times())) if self.pairs else float("nan")
+
+    def stats(self):
+        t = self.times()
+        return {"mean": float(np.mean(t)), "median": float(np.median(t)), "min": float(np.min(t))}
 
 
 def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
@@ -134,7 +141,7 @@ def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
     c = corr.Correlator(w.n_stations, w.n_pols, w.n_channels, w.n_integrate, prec)
     out = c.new_visibilities()
     A = w.n_integrate
-    ftimer, xtimer = Timer(torch), Timer(torch)
+    ftimer, xtimer, dtimer = Timer(torch), Timer(torch), Timer(torch)
 
     def step(timed):
         if timed:
@@ -146,7 +153,10 @@ def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
         c.xengine(A)
         if timed:
             xtimer.stop(s)
+            s = dtimer.start()
         c.dump(out, reset=True)
+        if timed:
+            dtimer.stop(s)
 
     for _ in range(warmup):
         step(False)
@@ -156,7 +166,8 @@ def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
         step(True)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    return c, out, inv, wall, ftimer.mean_ms(), xtimer.mean_ms()
+    timing = {"fengine_ms": ftimer.stats(), "xengine_ms": xtimer.stats(), "dump_ms": dtimer.stats()}
+    return c, out, inv, wall, ftimer.mean_ms(), xtimer.mean_ms(), timing
 
 
 def int8_valued(torch, shape, seed):
@@ -284,7 +295,21 @@ def cpu_baseline(torch, oracle, synth, w, volts, results, n_chan):
                    f"{C} channels, all {N} inputs x {A} spectra of the same integration; "
                    f"{cmacs:.3e} CMAC in {t:.2f} s"),
         "seconds": t,
+        "host": host_cpu(),
     }, errors
+
+
+def host_cpu():
+    """CPU model and logical CPU count of the host the oracle ran on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
 
 
 def run_batched(torch, corr, synth, steps_per_integration, reps=3):
@@ -398,7 +423,7 @@ def main():
     torch.cuda.synchronize()
 
     prec = args.precision
-    c, out, inv, wall, f_ms, x_ms = run_form(torch, corr, synth, w, prec, volts, args.steps, args.warmup)
+    c, out, inv, wall, f_ms, x_ms, timing = run_form(torch, corr, synth, w, prec, volts, args.steps, args.warmup)
     s2_main = None
     if prec == "int8":
         s2_main = 1.0 / synth.inv_scale(w, prec).astype(np.float64) ** 2
@@ -415,7 +440,8 @@ def main():
 
     forms = {}
     for fp in [f for f in args.forms.split(",") if f and f != prec]:
-        cf, of, invf, wall_f, f_ms_f, x_ms_f = run_form(torch, corr, synth, w, fp, volts, args.steps, args.warmup)
+        cf, of, invf, wall_f, f_ms_f, x_ms_f, timing_f = run_form(torch, corr, synth, w, fp, volts, args.steps,
+                                                                   args.warmup)
         s2 = None
         if fp == "int8":
             s2 = 1.0 / synth.inv_scale(w, fp).astype(np.float64) ** 2
@@ -427,7 +453,7 @@ def main():
                      "fengine_hbm_gbs": (N * A * C * (8 + 2 * ELEM_BYTES[fp])) / (f_ms_f * 1e-3) / 1e9,
                      "xengine_tcmacs": xt, "xengine_mfma_frac": 8 * xt / PEAK[fp],
                      "xengine_speedup_vs_fp32": x_ms / x_ms_f if prec == "fp32" else None,
-                     "step_tcmacs": cmacs / wall_f / 1e12}
+                     "step_tcmacs": cmacs / wall_f / 1e12, "timing": timing_f}
         log(f"{fp}: step {wall_f * 1e3:.3f} ms, F {f_ms_f:.3f} ms, X {x_ms_f:.3f} ms")
 
     equal = None
@@ -476,6 +502,7 @@ def main():
         "fengine_ms": f_ms,
         "xengine_tcmacs": cmacs / (x_ms * 1e-3) / 1e12,
         "fengine_hbm_gbs": (N * A * C * (8 + 2 * ELEM_BYTES[prec])) / (f_ms * 1e-3) / 1e9,
+        "timing": timing,
         "roofline": roofline,
         "forms": forms,
         "equal_accuracy": equal,
