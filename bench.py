@@ -256,6 +256,36 @@ def run_shapes(torch, corr, reps=3):
         log(f"shape {name} {prec}: X {ms:.3f} ms, {tc:.1f} TCMAC/s, {100 * 8 * tc / PEAK[prec]:.1f}% of MFMA peak")
         c.close()
         torch.cuda.empty_cache()
+    # Rectangle (cross-only) X-engine: inputs [512, 1024) against [0, 512),
+    # 2048 channels x 2048 spectra -- a space-division node's product.
+    for prec in ("int8", "fp16"):
+        N, C, A, h = 1024, 2048, 2048, 512
+        S = int8_valued(torch, (A, C, N, 2), seed=12)
+        if prec != "int8":
+            S = S.to(corr.SPECTRA_DTYPE[corr.PRECISIONS[prec]])
+        c = corr.Correlator(N // 2, 2, C, A, prec)
+        c.xengine(A, S)
+        del S
+        torch.cuda.empty_cache()
+        out = c.xengine_rect(h, N - h, 0, h, A)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            c.xengine_rect(h, N - h, 0, h, A, out=out)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sum(ts) / len(ts)
+        cm = (N - h) * h * C * A
+        tc = cm / (ms * 1e-3) / 1e12
+        res[f"{prec}/rect512x512-of-1024x2048x2048"] = {"rows": N - h, "cols": h, "channels": C, "spectra": A,
+                                                         "xengine_ms": ms, "xengine_tcmacs": tc,
+                                                         "mfma_frac": 8 * tc / PEAK[prec]}
+        log(f"rectangle 512x512 {prec}: X {ms:.3f} ms, {tc:.1f} TCMAC/s, {100 * 8 * tc / PEAK[prec]:.1f}% of MFMA peak")
+        del out
+        c.close()
+        torch.cuda.empty_cache()
     return res
 
 

@@ -188,14 +188,33 @@ CORR_API corr_status corr_dump_visibilities(corr_handle h, void *dst, int32_t ds
  */
 CORR_API corr_status corr_copy_spectra(corr_handle h, void *dst, int32_t dst_on_device);
 
+/*
+ * Cross-correlation of two disjoint input ranges: a rectangle of the
+ * triangle of pairs, the product a node forms in the paper's space-division
+ * models (Section 4), where one group of streams is correlated against
+ * another.  For every channel k, rows i in [i0, i0 + ni) and columns j in
+ * [j0, j0 + nj):
+ *     R[k][i - i0][j - j0] = s_k^2 sum_a conj(S_a,i[k]) S_a,j[k]      (Eq. 2)
+ * over the first n_spectra held spectra (the first index is conjugated, as in
+ * corr_xengine; i0 > j0 gives entries of the lower triangle, i0 < j0 their
+ * conjugates).  The ranges must not overlap (i0 + ni <= j0 or j0 + nj <= i0);
+ * for a triangle use corr_xengine.  d_out: caller-owned device buffer of
+ * C * ni * nj (re, im) pairs, float32 (int32 for CORR_INT8, unscaled), 8-byte
+ * aligned, [C][ni][nj] row-major; accumulate = 0 writes it, 1 adds to it.  The
+ * handle's accumulators and counters are not touched.  Errors:
+ * CORR_E_INVALID_ARG (ranges, overlap, pointer, flag), CORR_E_STATE (no or
+ * too few spectra held), CORR_E_OVERFLOW (int8 over 66572 spectra in one call).
+ */
+CORR_API corr_status corr_xengine_rect(corr_handle h, int32_t i0, int32_t ni, int32_t j0, int32_t nj,
+                                       int32_t n_spectra, void *d_out, int32_t accumulate);
+
 /* Number of spectra currently held, and spectra integrated since the last reset. */
 CORR_API corr_status corr_get_counts(corr_handle h, int32_t *n_held, int64_t *n_integrated);
 
 /*
  * X-engine block size.  The triangle of each channel is covered by square
  * blocks of `tile` inputs (64 or 128); 0 selects a default unless
- * corr_autotune has chosen: 64 for FP32, for N <= 64, and for int8 and FP8
- * with N <= 256; else 128.  Larger blocks reuse each operand more; smaller ones
+ * corr_autotune has chosen: 64 for FP32 and for N <= 64, else 128.  Larger blocks reuse each operand more; smaller ones
  * run more workgroups per CU and waste less on the diagonal and on ragged N.
  */
 CORR_API corr_status corr_set_tile(corr_handle h, int32_t tile);

@@ -43,7 +43,7 @@ ABI_FUNCTIONS = (
     "corr_destroy", "corr_fengine", "corr_xengine", "corr_dump_visibilities",
     "corr_copy_spectra", "corr_get_counts", "corr_status_string", "corr_last_error",
     "corr_set_tile", "corr_autotune", "corr_create_batched", "corr_batch_get",
-    "corr_xengine_batched", "corr_destroy_batched",
+    "corr_xengine_batched", "corr_destroy_batched", "corr_xengine_rect",
 )
 
 
@@ -103,7 +103,8 @@ def lib() -> ctypes.CDLL:
         L.corr_batch_get.argtypes = [P, i32, ctypes.POINTER(P)]
         L.corr_xengine_batched.argtypes = [P, ctypes.POINTER(i32)]
         L.corr_destroy_batched.argtypes = [P]
-        for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_xengine",
+        L.corr_xengine_rect.argtypes = [P, i32, i32, i32, i32, i32, P, i32]
+        for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_xengine", "corr_xengine_rect",
                   "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts", "corr_set_tile",
                   "corr_autotune", "corr_create_batched", "corr_batch_get", "corr_xengine_batched",
                   "corr_destroy_batched"):
@@ -202,6 +203,11 @@ def corr_xengine(h, spectra, n_spectra: int, inv_scale=None) -> None:
     _check(lib().corr_xengine(h, _ptr(spectra), int(n_spectra), _ptr(inv_scale)), "corr_xengine", h)
 
 
+def corr_xengine_rect(h, i0: int, ni: int, j0: int, nj: int, n_spectra: int, out, accumulate: bool = False) -> None:
+    _check(lib().corr_xengine_rect(h, int(i0), int(ni), int(j0), int(nj), int(n_spectra), _ptr(out),
+                                   int(bool(accumulate))), "corr_xengine_rect", h)
+
+
 def corr_dump_visibilities(h, dst, reset: bool = True, dst_on_device: int | None = None) -> None:
     dev = _on_device(dst) if dst_on_device is None else int(dst_on_device)
     _check(lib().corr_dump_visibilities(h, _ptr(dst), dev, int(bool(reset))), "corr_dump_visibilities", h)
@@ -272,6 +278,15 @@ class Correlator:
 
     def xengine(self, n_spectra, spectra=None, inv_scale=None):
         corr_xengine(self.handle, spectra, n_spectra, inv_scale)
+
+    def xengine_rect(self, i0, ni, j0, nj, n_spectra, out=None, accumulate=False):
+        """Rows [i0, i0+ni) against columns [j0, j0+nj) of the held spectra:
+        a [C][ni][nj][2] tensor (float32; int32 for int8), written or added to."""
+        if out is None:
+            dt = torch.int32 if self.precision == CORR_INT8 else torch.float32
+            out = torch.empty((self.n_channels, ni, nj, 2), dtype=dt, device="cuda")
+        corr_xengine_rect(self.handle, i0, ni, j0, nj, n_spectra, out, accumulate)
+        return out
 
     def visibility_shape(self):
         """Shape of a dump as a tensor whose last axis is (re, im)."""

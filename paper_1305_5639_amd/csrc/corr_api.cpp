@@ -142,14 +142,12 @@ bool default_dump(const corr_params *p) { return p->layout == CORR_TRI_LOWER && 
 bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
 // Default block size when none was set or tuned, from measured X-engine
-// speed on MI355X at 256..1024 inputs: 64-input blocks (four workgroups per
-// CU) win for FP32, and for int8 and FP8 up to 256 inputs; 128-input blocks
-// (more operand reuse) win for FP16 and for larger int8 and FP8 arrays.
+// speed on MI355X at 256..1024 inputs: 64-input blocks (five workgroups per
+// CU) win for FP32, 128-input blocks (eight 64x32 waves, more operand reuse)
+// for the FP16, int8 and FP8 forms.
 int effective_tile(const corr_ctx *h) {
     if (h->tile) return h->tile;
-    if (h->N <= 64 || h->prec == P_FP32) return 64;
-    if ((h->prec == P_INT8 || h->prec == P_FP8) && h->N <= 256) return 64;
-    return 128;
+    return (h->N <= 64 || h->prec == P_FP32) ? 64 : 128;
 }
 
 const float *x_scale(const corr_ctx *h) {
@@ -395,6 +393,28 @@ corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra
     if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
     h->acc_zero = false;
     h->n_integrated += n_spectra;
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_xengine_rect(corr_handle h, int32_t i0, int32_t ni, int32_t j0, int32_t nj, int32_t n_spectra,
+                              void *d_out, int32_t accumulate) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (ni < 1 || nj < 1 || i0 < 0 || j0 < 0 || (int64_t)i0 + ni > h->N || (int64_t)j0 + nj > h->N)
+        return fail(h, CORR_E_INVALID_ARG, "row and column ranges must be non-empty and within the inputs");
+    if (!((int64_t)i0 + ni <= j0 || (int64_t)j0 + nj <= i0))
+        return fail(h, CORR_E_INVALID_ARG, "row and column ranges overlap: use corr_xengine for a triangle");
+    if (!d_out || !aligned(d_out, 8)) return fail(h, CORR_E_INVALID_ARG, "d_out must be an 8-byte aligned device pointer");
+    if (accumulate != 0 && accumulate != 1) return fail(h, CORR_E_INVALID_ARG, "accumulate must be 0 or 1");
+    if (n_spectra < 1) return fail(h, CORR_E_INVALID_ARG, "n_spectra must be >= 1");
+    if (h->n_held == 0) return fail(h, CORR_E_STATE, "no spectra held: call corr_fengine first");
+    if (n_spectra > h->n_held) return fail(h, CORR_E_STATE, "n_spectra exceeds the spectra held");
+    if (h->prec == P_INT8 && n_spectra > CORR_INT8_MAX_INTEGRATE)
+        return fail(h, CORR_E_OVERFLOW, "int8 rectangle over more than 66572 spectra");
+    const hipError_t e = launch_xengine_rect(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->n_tb_cap,
+                                             h->spec, x_scale(h), d_out, accumulate ? 0 : 1, i0, ni, j0, nj,
+                                             h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "rectangle launch");
     h->err.clear();
     return CORR_OK;
 }

@@ -61,6 +61,13 @@ hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t l
 hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
                           const float *scale2, void *acc, int first_call, hipStream_t stream);
 
+// Rectangle X-engine: rows [r0, r0 + ni) against columns [c0, c0 + nj) of the
+// held spectra (disjoint ranges), into out [C][ni][nj] (re, im) pairs, written
+// when first_call, else added to.
+hipError_t launch_xengine_rect(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+                               const float *scale2, void *out, int first_call, int r0, int ni, int c0, int nj,
+                               hipStream_t stream);
+
 // One sub-array of a batched X-engine launch.  Items [item_begin,
 // item_begin + C * n_tiles) are (channel, block) pairs of this sub-array.
 // Accelerator complex dies (XCDs), each with its own L2; workgroups are

@@ -222,20 +222,29 @@ template <int n> __device__ __forceinline__ void wait_vm() {
     __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
 }
 
+// Where a block's results go.  Triangle (RECT = false): the lower-triangle
+// product i(i+1)/2 + j of rows and columns below N with j <= i, B per
+// channel.  Rectangle (RECT = true): rows [r0, r_end) x columns [c0, c_end),
+// row-major, (i - r0) (c_end - c0) + (j - c0), B per channel; the two ranges
+// do not overlap, so no pair is an auto.
+struct OutMap {
+    int r0, r_end, c0, c_end;
+};
+
 // The whole K loop and epilogue of one TILE x TILE block of channel k, rows
 // I0.., columns J0.., by the waves of WaveGrid<TILE>.
 // Time blocks stream through a two-slot LDS ring by direct global-to-LDS
 // copies: the copy of time block t + 1 is issued when block t starts and
 // lands while its MFMAs run.  The copies bypass registers, so the block
-// keeps two workgroups per CU with the accumulators and fragments of a
-// 64x64 quarter per wave.  Both operand slabs are
-// always copied (a diagonal block copies the same rows twice).  Rows past N
-// copy row N - 1; they only feed outputs that are not written.  In the last
-// time block, spectra past the valid count are zeroed in LDS once it lands.
-template <int PREC, int TILE>
+// keeps two workgroups per CU.  Both operand slabs are always copied (a
+// diagonal block copies the same rows twice).  Rows past N copy row N - 1;
+// they only feed outputs that are not written.  In the last time block,
+// spectra past the valid count are zeroed in LDS once it lands.
+template <int PREC, int TILE, bool RECT = false>
 __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ base_k, int N, int n_tb, int tv,
                                      int I0, int J0, int k, const float *__restrict__ scale2,
-                                     void *__restrict__ acc_out, int64_t B, int first_call, int tid) {
+                                     void *__restrict__ acc_out, int64_t B, int first_call, int tid,
+                                     OutMap om = OutMap{}) {
     constexpr int NT = kNT, RB = kRB, CPP = kCPP;
     using Acc = typename XT<PREC, NT>::Acc;
     constexpr int ES = PREC == P_FP32 ? 4 : (PREC == P_FP16 ? 2 : 1);
@@ -249,7 +258,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     const int wave = tid >> 6, lane = tid & 63;
     const int wi = wave / WC, wj = wave % WC;
     const int m = lane & 31, h = lane >> 5;
-    const bool diag = I0 == J0;
+    const bool diag = !RECT && I0 == J0;
     // on a diagonal block, a wave whose columns all lie right of its rows
     // idles; one whose first 32 rows do skips that row block
     const bool active = !(diag && 32 * wj > wi * QS + QS - 1);
@@ -338,9 +347,9 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
 
     // Epilogue: element r of a 32x32 block is (row 8(r/4) + 4h + r%4, column m).
     // Rows go in batches of EH; each batch's accumulator reads are issued
-    // before any of its writes.  Elements outside the triangle or past N read a
-    // valid address and are not written.  Offsets within a channel fit 32 bits
-    // (N(N+1)/2 < 2^31 for N <= 8192).
+    // before any of its writes.  Elements outside the triangle (rectangle) or
+    // past N read a valid address and are not written.  Offsets within a
+    // channel fit 32 bits (N(N+1)/2 and N^2 < 2^31 for N <= 8192).
     using E = typename std::conditional<PREC == P_INT8, int, float>::type;
     typedef E T2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(1))) T2 gT2;
@@ -361,9 +370,17 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
             for (int q = 0; q < EH; ++q) {
                 const int r = EH * hh + q;
                 const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                const bool in = i < N && j <= i;
+                bool in;
+                int o;
+                if constexpr (RECT) {
+                    in = i < om.r_end && j < om.c_end;
+                    o = (i - om.r0) * (om.c_end - om.c0) + (j - om.c0);
+                } else {
+                    in = i < N && j <= i;
+                    o = i * (i + 1) / 2 + j;
+                }
                 ok |= (uint32_t)in << q;
-                idx[q] = in ? i * (i + 1) / 2 + j : 0;
+                idx[q] = in ? o : 0;
             }
             T2 old[EH];
             if (!first_call) {
@@ -375,10 +392,11 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
                 const int r = EH * hh + q;
                 const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 T2 v;
+                const bool auto_ = !RECT && i == j;
                 if constexpr (PREC == P_INT8) {
-                    v = T2{re[f][r], i == j ? 0 : im[f][r]};
+                    v = T2{re[f][r], auto_ ? 0 : im[f][r]};
                 } else {
-                    v = T2{re[f][r] * s2, i == j ? 0.0f : im[f][r] * s2};
+                    v = T2{re[f][r] * s2, auto_ ? 0.0f : im[f][r] * s2};
                 }
                 if (!first_call) {
                     v.x += old[q].x;
@@ -414,6 +432,22 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
     tri_block(w % n_tiles, bi, bj);
     tile<PREC, TILE>(smem, spec + (int64_t)k * k_stride, N, n_tb, tv, bi * TILE, bj * TILE, k, scale2, acc_out,
                      B, first_call, threadIdx.x);
+}
+
+// Rectangle X-engine: rows [r0, r0 + ni) against columns [c0, c0 + nj) in
+// TILE x TILE blocks (nbi x nbj per channel), XCD-major like xengine_kernel.
+template <int PREC, int TILE>
+__global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(4))) void xengine_rect_kernel(
+    const uint8_t *__restrict__ spec, int N, int nbi, int nbj, int n_work, int n_tb, int tv, int64_t k_stride,
+    const float *__restrict__ scale2, void *__restrict__ out, int64_t B, int first_call, OutMap om) {
+    __shared__ __attribute__((aligned(16))) uint8_t smem[ring_bytes(TILE)];
+    const int per = (n_work + 7) / 8;
+    const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (w >= n_work) return;
+    const int nb = nbi * nbj;
+    const int k = w / nb, bi = (w % nb) / nbj, bj = w % nbj;
+    tile<PREC, TILE, true>(smem, spec + (int64_t)k * k_stride, N, n_tb, tv, om.r0 + bi * TILE, om.c0 + bj * TILE, k,
+                           scale2, out, B, first_call, threadIdx.x, om);
 }
 
 // Persistent X-engine over many sub-arrays with blocks of TILE inputs, so
@@ -504,6 +538,47 @@ hipError_t launch_xp(int tile, int C, int N, int n_spectra, int n_tb_cap, const 
 }
 
 }  // namespace
+
+template <int PREC, int TILE>
+hipError_t launch_rect_t(int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
+                         void *out, int first_call, int r0, int ni, int c0, int nj, hipStream_t stream) {
+    const int TB = time_block(PREC);
+    const int n_tb = (n_spectra + TB - 1) / TB;
+    const int tv = n_spectra - (n_tb - 1) * TB;
+    const int nbi = (ni + TILE - 1) / TILE, nbj = (nj + TILE - 1) / TILE;
+    const int64_t n_work = (int64_t)C * nbi * nbj;
+    if (n_tb <= 0 || n_work <= 0 || n_work > ((int64_t)1 << 30) || r0 < 0 || c0 < 0 || r0 + ni > N || c0 + nj > N)
+        return hipErrorInvalidValue;
+    const int grid = (int)((n_work + 7) / 8) * 8;
+    hipLaunchKernelGGL((xengine_rect_kernel<PREC, TILE>), dim3(grid), dim3(WaveGrid<TILE>::THREADS), 0, stream,
+                       static_cast<const uint8_t *>(spec), N, nbi, nbj, (int)n_work, n_tb, tv,
+                       channel_stride(n_tb_cap, N), scale2, out, (int64_t)ni * nj, first_call,
+                       OutMap{r0, r0 + ni, c0, c0 + nj});
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_rect_p(int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+                         const float *scale2, void *out, int first_call, int r0, int ni, int c0, int nj,
+                         hipStream_t stream) {
+    if (tile == 64)
+        return launch_rect_t<PREC, 64>(C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+    if (tile == 128)
+        return launch_rect_t<PREC, 128>(C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_xengine_rect(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+                               const float *scale2, void *out, int first_call, int r0, int ni, int c0, int nj,
+                               hipStream_t stream) {
+    switch (prec) {
+    case P_FP32: return launch_rect_p<P_FP32>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+    case P_FP16: return launch_rect_p<P_FP16>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+    case P_FP8: return launch_rect_p<P_FP8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+    case P_INT8: return launch_rect_p<P_INT8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
                           const float *scale2, void *acc, int first_call, hipStream_t stream) {
