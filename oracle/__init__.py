@@ -1,7 +1,8 @@
 """FX-correlator oracle -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
 
 Plain float64 / exact-integer statements of the correlator hot path of Wang &
-Harris (Exp. Astron. 2013): the F-engine DFT (Section 2, Eq. 1), the X-engine
+Harris (Exp. Astron. 2013): the F-engine DFT (Section 2, Eq. 1, for complex
+samples and for the 8-bit real samples of Section 5), the X-engine
 correlation over the triangle of non-redundant pairs (Section 2, Eq. 2 and
 Section 4), the requantisers of the reduced-precision forms, and the emission
 of the visibility triangle in the supported layouts and orders.
@@ -51,6 +52,7 @@ def lib() -> ctypes.CDLL:
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int, ctypes.c_int64
         L.oracle_fengine.argtypes = [P, i64, i32, i32, i32, P, i32, P]
+        L.oracle_fengine_real8.argtypes = [P, i64, i32, i32, i32, P, i32, P]
         L.oracle_xengine_f64.argtypes = [P, i32, i32, i32, P]
         L.oracle_xengine_i8.argtypes = [P, i32, i32, i32, P]
         L.oracle_round_format.argtypes = [ctypes.c_double, i32, i32, ctypes.c_double]
@@ -93,6 +95,26 @@ def fengine(volts: np.ndarray, C: int, n_spectra: int, chans=None) -> np.ndarray
         raise ValueError("channel out of range")
     S = np.empty((n_spectra, n_inputs, ch.size), dtype=np.complex128)
     lib().oracle_fengine(_ptr(v), ld, n_inputs, C, n_spectra, _ptr(ch), ch.size, _ptr(S))
+    return S
+
+
+def fengine_real8(samples: np.ndarray, C: int, n_spectra: int, chans=None) -> np.ndarray:
+    """Real-input Eq. 1 (Section 5: 8-bit real samples): direct DFT of length 2C
+    of consecutive 2C-sample blocks.
+
+    samples: int8 [n_inputs][ld] with ld >= n_spectra*2C.
+    chans: channels to evaluate, each in [0, C] (default 0..C-1; C is Nyquist).
+    Returns complex128 S[a][p][c].
+    """
+    x = np.ascontiguousarray(samples, dtype=np.int8)
+    n_inputs, ld = x.shape
+    if ld < n_spectra * 2 * C:
+        raise ValueError("sample rows shorter than n_spectra*2C")
+    ch = np.arange(C, dtype=np.int32) if chans is None else np.ascontiguousarray(chans, dtype=np.int32)
+    if ch.size and (ch.min() < 0 or ch.max() > C):
+        raise ValueError("channel out of range")
+    S = np.empty((n_spectra, n_inputs, ch.size), dtype=np.complex128)
+    lib().oracle_fengine_real8(_ptr(x), ld, n_inputs, C, n_spectra, _ptr(ch), ch.size, _ptr(S))
     return S
 
 

@@ -8,7 +8,9 @@
  *   - F-engine, Section 2 Eq. 1:  S[k] = sum_{n=0}^{C-1} s[n] exp(-j 2 pi k n / C),
  *     a direct DFT in float64, applied to consecutive non-overlapping blocks of
  *     C samples (block a uses samples [aC, (a+1)C)), natural channel order, no
- *     normalisation, no window.
+ *     normalisation, no window.  The real-input form (Section 5: 8-bit real
+ *     samples, transform length 256) takes blocks of 2C real samples and keeps
+ *     channels 0..C of their length-2C DFT.
  *   - X-engine, Section 2 Eq. 2:  C_ij[k] = sum_{a=0}^{A-1} conj(S_{a,i}[k]) S_{a,j}[k],
  *     conjugate on the first index, summed (not averaged) over A spectra, over
  *     the triangle of non-redundant pairs including the autos (Section 4).
@@ -94,6 +96,55 @@ void oracle_fengine(const float *volts, int64_t ld, int n_inputs, int C,
                     m -= C;
             }
             double *o = S + 2 * ((ap) * n_chans + c);
+            o[0] = re;
+            o[1] = im;
+        }
+    }
+    free(w);
+}
+
+/*
+ * Real-input form of Eq. 1 (Section 5: the test streams are 8-bit real
+ * samples and the transform length is 256).  Block a of input p is the 2C
+ * real samples x_p[a*2C .. a*2C + 2C); its spectrum is the DFT of length 2C,
+ *
+ *   X[a][p][c] = sum_{n=0}^{2C-1} x_p[a*2C + n] * exp(-j 2 pi k n / (2C)),
+ *   k = chans[c] in [0, C]  (C itself is the Nyquist channel),
+ *
+ * evaluated directly in float64 with the argument reduced exactly,
+ * m = (k n) mod 2C, as in oracle_fengine.
+ *   x : int8 [n_inputs][ld] real samples.
+ *   S : complex128 [n_spectra][n_inputs][n_chans] output.
+ */
+void oracle_fengine_real8(const int8_t *x, int64_t ld, int n_inputs, int C, int n_spectra,
+                          const int *chans, int n_chans, double *S)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const int L = 2 * C;
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)L);
+    for (int m = 0; m < L; ++m) {
+        w[2 * m + 0] = cos(two_pi * (double)m / (double)L);
+        w[2 * m + 1] = -sin(two_pi * (double)m / (double)L);
+    }
+    const int64_t total = (int64_t)n_spectra * n_inputs;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t ap = 0; ap < total; ++ap) {
+        const int a = (int)(ap / n_inputs);
+        const int p = (int)(ap % n_inputs);
+        const int8_t *s = x + (int64_t)p * ld + (int64_t)a * L;
+        for (int c = 0; c < n_chans; ++c) {
+            const int k = chans[c];
+            double re = 0.0, im = 0.0;
+            int m = 0; /* m = (k n) mod 2C */
+            for (int n = 0; n < L; ++n) {
+                const double v = (double)s[n];
+                re += v * w[2 * m];
+                im += v * w[2 * m + 1];
+                m += k;
+                if (m >= L)
+                    m -= L;
+            }
+            double *o = S + 2 * (ap * n_chans + c);
             o[0] = re;
             o[1] = im;
         }

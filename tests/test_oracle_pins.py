@@ -105,6 +105,89 @@ def test_dft_channel_subset_and_blocks(orc):
         assert _rel(full[a], ref) < 1e-12
 
 
+# ------------------------------------------- Eq. 1, 8-bit real samples ----
+def _i8(rng, shape, lo=-128, hi=128):
+    return rng.integers(lo, hi, shape, dtype=np.int8)
+
+
+@pytest.mark.parametrize("C", [2, 8, 64, 128, 512])
+def test_real8_matches_numpy_rfft(orc, C):
+    """Library special case: numpy's real FFT of length 2C (forward,
+    unnormalised, bins 0..C), blocks of 2C samples from rows with ld > A*2C."""
+    rng = np.random.default_rng(100 + C)
+    A, N = 3, 4
+    ld = A * 2 * C + 5
+    x = _i8(rng, (N, ld))
+    chans = np.arange(C + 1)
+    S = orc.fengine_real8(x, C, A, chans)                              # [A][N][C+1]
+    ref = np.fft.rfft(x[:, :A * 2 * C].astype(np.float64).reshape(N, A, 2 * C), axis=-1).transpose(1, 0, 2)
+    assert _rel(S, ref) < 1e-12
+    assert np.array_equal(orc.fengine_real8(x, C, A), S[:, :, :C])      # default: channels 0..C-1
+
+
+@pytest.mark.parametrize("C,n0", [(4, 0), (16, 5), (128, 255), (128, 17)])
+def test_real8_impulse(orc, C, n0):
+    """x[n0] = 1 gives exp(-j pi k n0 / C) at every channel 0..C."""
+    x = np.zeros((1, 2 * C), np.int8)
+    x[0, n0] = 1
+    k = np.arange(C + 1)
+    S = orc.fengine_real8(x, C, 1, k)[0, 0]
+    ref = np.exp(-1j * np.pi * ((k * n0) % (2 * C)) / C)
+    assert np.max(np.abs(S - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("C", [4, 128])
+def test_real8_dc_nyquist_quarter(orc, C):
+    """Closed forms with integer samples: a constant lands only in channel 0
+    (2C times it), (-1)^n only in the Nyquist channel C, and the period-4
+    sequences cos(pi n/2) = 1,0,-1,0 and sin(pi n/2) = 0,1,0,-1 only in
+    channel C/2, as C and -jC."""
+    n = np.arange(2 * C)
+    x = np.stack([np.full(2 * C, -7), (-1) ** n, [1, 0, -1, 0][0:4] * (C // 2),
+                  [0, 1, 0, -1] * (C // 2)]).astype(np.int8)
+    k = np.arange(C + 1)
+    S = orc.fengine_real8(x, C, 1, k)[0]
+    ref = np.zeros((4, C + 1), complex)
+    ref[0, 0] = -7 * 2 * C
+    ref[1, C] = 2 * C
+    ref[2, C // 2] = C
+    ref[3, C // 2] = -1j * C
+    assert np.max(np.abs(S - ref)) < 1e-12
+
+
+def test_real8_equals_complex_dft_of_real_samples(orc):
+    """The real-input transform equals the (separately pinned) complex DFT of
+    length 2C of the same samples with zero imaginary part, channels 0..C."""
+    rng = np.random.default_rng(11)
+    C, A, N = 64, 2, 3
+    x = _i8(rng, (N, A * 2 * C))
+    k = np.arange(C + 1)
+    S = orc.fengine_real8(x, C, A, k)
+    Z = orc.fengine(x.astype(np.complex64), 2 * C, A, k)
+    assert _rel(S, Z) < 1e-13
+
+
+def test_real8_parseval(orc):
+    """For real samples: 2C sum x^2 = |X_0|^2 + |X_C|^2 + 2 sum_{0<k<C} |X_k|^2."""
+    rng = np.random.default_rng(12)
+    C, A, N = 128, 3, 2
+    x = _i8(rng, (N, A * 2 * C))
+    S = orc.fengine_real8(x, C, A, np.arange(C + 1))
+    P = np.abs(S) ** 2
+    lhs = P[..., 0] + P[..., C] + 2 * P[..., 1:C].sum(-1)                # [A][N]
+    rhs = 2 * C * (x.astype(np.float64).reshape(N, A, 2 * C) ** 2).sum(-1).T
+    assert _rel(lhs, rhs) < 1e-12
+    assert np.max(np.abs(S[..., 0].imag)) < 1e-9 and np.max(np.abs(S[..., C].imag)) < 1e-9
+
+
+def test_real8_rejects_bad_arguments(orc):
+    x = np.zeros((1, 16), np.int8)
+    with pytest.raises(ValueError):
+        orc.fengine_real8(x, 8, 2)
+    with pytest.raises(ValueError):
+        orc.fengine_real8(x, 8, 1, [9])
+
+
 # ---------------------------------------------------------------- Eq. 2 ----
 def _brute_xcorr(S):
     """Python-loop statement of Eq. 2 on complex numbers (tiny sizes only)."""
