@@ -67,6 +67,8 @@ def parse():
                     help="graph replays per integration in the batched section")
     ap.add_argument("--cpu-channels", type=int, default=768)
     ap.add_argument("--no-equal-accuracy", action="store_true")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the 8-bit real-sample section (128 to 3072 streams, transform length 256)")
     ap.add_argument("--no-shapes", action="store_true",
                     help="skip the X-engine timings at the 512- and 1024-input shapes")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -289,6 +291,59 @@ def run_shapes(torch, corr, reps=3):
     return res
 
 
+def run_paper_workload(torch, corr, synth, reps=3):
+    """The paper's own test streams (Section 5): 8-bit real samples, transform
+    length 256 (128 channels), 1024 spectra, 128 to 3072 streams; the
+    real-input F-engine and the X-engine in FP32 (the paper's precision) and
+    int8.  Rates in the paper's counting too: 2.5 L log2 L flops per real
+    transform of length L and 8 per CMAC."""
+    res = {}
+    for name in ("paper-128-r256", "paper-512-r256", "paper-2048-r256", "paper-3072-r256"):
+        w = synth.REAL_WORKLOADS[name]
+        N, C, A = w.n_streams, w.n_channels, w.n_integrate
+        L = 2 * C
+        x = synth.real8_samples(w, device="cuda")
+        for prec in ("fp32", "int8"):
+            inv = torch.from_numpy(synth.real8_inv_scale(w, prec)).to("cuda") if prec == "int8" else None
+            c = corr.Correlator(N, 1, C, A, prec)
+            dst = c.new_visibilities()
+            c.fengine_real8(x, A, inv)                 # warm-up
+            c.xengine(A)
+            c.dump(dst, reset=True)
+            ft, xt = Timer(torch), Timer(torch)
+            for _ in range(reps):
+                s = ft.start()
+                c.fengine_real8(x, A, inv)
+                ft.stop(s)
+                s = xt.start()
+                c.xengine(A)
+                xt.stop(s)
+                c.dump(dst, reset=True)
+            torch.cuda.synchronize()
+            f_ms, x_ms = ft.mean_ms(), xt.mean_ms()
+            step = f_ms + x_ms
+            cm = w.cmacs
+            flops = N * A * 2.5 * L * math.log2(L) + 8.0 * cm
+            res[f"{prec}/{name}"] = {
+                "streams": N, "transform_length": L, "channels": C, "spectra": A,
+                "fengine_ms": f_ms, "xengine_ms": x_ms, "fx_ms": step,
+                "xengine_tcmacs": cm / (x_ms * 1e-3) / 1e12,
+                "xengine_mfma_frac": 8 * cm / (x_ms * 1e-3) / 1e12 / PEAK[prec],
+                "fengine_hbm_gbs": N * A * (L + 2 * C * ELEM_BYTES[prec]) / (f_ms * 1e-3) / 1e9,
+                "fx_gflops_paper_count": flops / (step * 1e-3) / 1e9,
+                "samples_per_s_per_stream": A * L / (step * 1e-3)}
+            log(f"paper workload {name} {prec}: F {f_ms:.3f} ms, X {x_ms:.3f} ms, "
+                f"{res[f'{prec}/{name}']['fx_gflops_paper_count']:.0f} GFLOPS (paper count), "
+                f"{res[f'{prec}/{name}']['samples_per_s_per_stream'] / 1e6:.1f} Msample/s per stream")
+            del dst
+            c.close()
+            torch.cuda.empty_cache()
+        del x
+        torch.cuda.empty_cache()
+    return {"reference": "paper: ~105 GFLOPS for F + X on one Tesla C2075 (single precision, 8-bit "
+                         "real samples, transform length 256); context, not a target", **res}
+
+
 def cpu_baseline(torch, oracle, synth, w, volts, results, n_chan):
     """The oracle on a channel sample of the same integration; errors per form."""
     C, N, A = w.n_channels, w.n_inputs, w.n_integrate
@@ -494,6 +549,10 @@ def main():
     if not args.no_shapes:
         shapes = run_shapes(torch, corr)
 
+    paper = None
+    if not args.no_paper:
+        paper = run_paper_workload(torch, corr, synth)
+
     batched = None
     if not args.no_batched:
         log("batched: 64 uneven sub-arrays")
@@ -538,6 +597,7 @@ def main():
         "equal_accuracy": equal,
         "xengine_shapes": shapes,
         "batched": batched,
+        "paper_workload": paper,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

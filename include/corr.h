@@ -148,6 +148,23 @@ CORR_API corr_status corr_fengine(corr_handle h, const void *d_volts, int64_t ld
                          int32_t n_spectra, const float *d_inv_scale);
 
 /*
+ * F-engine on 8-bit real samples (Section 5: every test stream is 8-bit real
+ * integers and the transform length is 256), with the same requantise
+ * epilogue and the same held spectra as corr_fengine.
+ *   d_samples   : int8 real samples, [n_inputs][ld_samples]; spectrum a of
+ *                 input p is the length-2C DFT (Eq. 1 with 2C points) of
+ *                 samples [a*2C, (a+1)*2C) of row p, of which channels
+ *                 0 .. C-1 are kept (the Nyquist channel C is dropped), C the
+ *                 handle's n_channels.  2-byte aligned.
+ *   ld_samples  : row stride in samples (bytes), even, >= n_spectra*2C.
+ *   n_spectra, d_inv_scale : as for corr_fengine.
+ * The spectra replace the handle's previous spectra; corr_xengine then
+ * correlates them as usual.
+ */
+CORR_API corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, int64_t ld_samples,
+                                        int32_t n_spectra, const float *d_inv_scale);
+
+/*
  * X-engine (Eq. 2): add n_spectra spectra into the accumulators.
  *   d_spectra   : NULL = the first n_spectra spectra of the last corr_fengine
  *                 (n_spectra above that call's count is CORR_E_STATE); else

@@ -33,6 +33,7 @@ struct corr_ctx {
     void *acc = nullptr;
     size_t acc_bytes = 0;
     float2 *twiddle = nullptr;
+    float2 *twiddle2n = nullptr;       // exp(-j pi k / C), k < C (real-input F-engine)
     float *scale2 = nullptr;          // s_k^2 of the F-engine's spectra
     float *scale2_user = nullptr;     // s_k^2 of caller spectra
     void *dump_tmp = nullptr;         // staging for converted dumps to host
@@ -293,18 +294,23 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
     if ((e = hipMalloc(&h->acc, acc_bytes)) != hipSuccess)
         return cleanup_fail(e == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP, "hipMalloc accumulators failed");
     if ((e = hipMalloc(&h->twiddle, (size_t)C * sizeof(float2))) != hipSuccess ||
+        (e = hipMalloc(&h->twiddle2n, (size_t)C * sizeof(float2))) != hipSuccess ||
         (e = hipMalloc(&h->scale2, (size_t)C * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&h->scale2_user, (size_t)C * sizeof(float))) != hipSuccess)
         return cleanup_fail(CORR_E_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
 
     // Twiddles W[m] = exp(-j 2 pi m / C), computed in float64, rounded to float32.
-    std::vector<float2> tw(C);
+    // W2[k] = exp(-j 2 pi k / 2C) for the real-input split, the same way.
+    std::vector<float2> tw(C), tw2(C);
     const double two_pi = 6.283185307179586476925286766559;
     for (int m = 0; m < C; ++m) {
         const double ang = two_pi * (double)m / (double)C;
         tw[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+        const double ang2 = two_pi * (double)m / (2.0 * (double)C);
+        tw2[m] = make_float2((float)std::cos(ang2), (float)-std::sin(ang2));
     }
-    if ((e = hipMemcpy(h->twiddle, tw.data(), (size_t)C * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpy(h->twiddle, tw.data(), (size_t)C * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->twiddle2n, tw2.data(), (size_t)C * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup_fail(CORR_E_HIP, std::string("hipMemcpy twiddles: ") + hipGetErrorString(e));
     *out = h;
     return CORR_OK;
@@ -317,6 +323,7 @@ static void destroy_ctx(corr_ctx *h) {
     (void)hipFree(h->spec);
     (void)hipFree(h->acc);
     (void)hipFree(h->twiddle);
+    (void)hipFree(h->twiddle2n);
     (void)hipFree(h->scale2);
     (void)hipFree(h->scale2_user);
     (void)hipFree(h->dump_tmp);
@@ -350,6 +357,31 @@ corr_status corr_fengine(corr_handle h, const void *d_volts, int64_t ld_samples,
     e = launch_fengine(h->prec, h->C, h->N, static_cast<const float2 *>(d_volts), ld_samples, n_spectra,
                        d_inv_scale, h->twiddle, h->spec, h->n_tb_cap, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine launch");
+    h->n_held = n_spectra;
+    h->held_from_fengine = true;
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, int64_t ld_samples, int32_t n_spectra,
+                               const float *d_inv_scale) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (!d_samples) return fail(h, CORR_E_INVALID_ARG, "d_samples is NULL");
+    if (!aligned(d_samples, 2)) return fail(h, CORR_E_INVALID_ARG, "d_samples must be 2-byte aligned");
+    if (ld_samples % 2) return fail(h, CORR_E_INVALID_ARG, "ld_samples must be even");
+    if (d_inv_scale && !aligned(d_inv_scale, 4)) return fail(h, CORR_E_INVALID_ARG, "d_inv_scale misaligned");
+    if (n_spectra < 1 || n_spectra > h->p.n_integrate)
+        return fail(h, CORR_E_INVALID_ARG, "n_spectra must be in 1..n_integrate");
+    if (ld_samples < (int64_t)n_spectra * 2 * h->C)
+        return fail(h, CORR_E_INVALID_ARG, "ld_samples < n_spectra * 2 * n_channels");
+    if (h->prec == P_INT8 && !d_inv_scale)
+        return fail(h, CORR_E_INVALID_ARG, "int8 needs a per-channel scale");
+
+    hipError_t e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
+    e = launch_fengine_real8(h->prec, h->C, h->N, d_samples, ld_samples, n_spectra, d_inv_scale, h->twiddle,
+                             h->twiddle2n, h->spec, h->n_tb_cap, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "fengine_real8 launch");
     h->n_held = n_spectra;
     h->held_from_fengine = true;
     h->err.clear();

@@ -22,6 +22,12 @@
 // a contiguous range of work items), so the workgroups that fill the same
 // 128-byte spectra rows run on one XCD at about the same time and their
 // partial-row stores merge in that XCD's L2.
+//
+// Real-input form (Section 5: 8-bit real samples, transform length 2C): the
+// 2C samples of a block are read as C complex values z[n] = x[2n] + j x[2n+1]
+// straight from the int8 stream, transformed by the same C-point FFT, and the
+// length-2C spectrum's channels k < C are split out of it after the last
+// pass (one more LDS round trip for the partner value Z[C - k]).
 #include "corr_internal.h"
 
 namespace corr {
@@ -129,9 +135,15 @@ __device__ __forceinline__ int lidx(int t, int i) {
 
 // First Stockham pass, radix R: butterfly (t, j) takes x[t][j + r C/R] straight
 // from global memory (spectra past n_spectra read as zero) and does an R-point
-// DFT; no twiddles precede the first pass.
-template <int C, int T, int R>
-__device__ __forceinline__ void first_pass(float2 *v, const float2 *__restrict__ src, int a0, int n_spectra,
+// DFT; no twiddles precede the first pass.  The loads are unconditional (a
+// padding spectrum reads spectrum 0, which always exists, and is then zeroed)
+// so that all of a thread's loads are in flight together: a load under a
+// branch whose value is converted inside it would be waited for one by one.
+__device__ __forceinline__ float2 to_f2(float2 x) { return x; }
+__device__ __forceinline__ float2 to_f2(char2 x) { return make_float2((float)x.x, (float)x.y); }
+
+template <int C, int T, int R, typename Src>
+__device__ __forceinline__ void first_pass(float2 *v, const Src *__restrict__ src, int a0, int n_spectra,
                                            int tid) {
     constexpr int Q = kPerThread / R, CR = C / R;
 #pragma unroll
@@ -140,9 +152,15 @@ __device__ __forceinline__ void first_pass(float2 *v, const float2 *__restrict__
         bfly_index<C, T, R, false>(tid + kThreads * q, t, j);
         float2 *x = v + q * R;
         const bool ok = (a0 + t) < n_spectra;
-        const float2 *row = src + (int64_t)(a0 + t) * C + j;
+        const Src *row = src + (int64_t)(ok ? a0 + t : 0) * C + j;
+        Src raw[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = ok ? row[r * CR] : make_float2(0.f, 0.f);
+        for (int r = 0; r < R; ++r) raw[r] = row[r * CR];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float2 f = to_f2(raw[r]);
+            x[r] = make_float2(ok ? f.x : 0.f, ok ? f.y : 0.f);
+        }
         Dft<R>::run(x);
     }
 }
@@ -234,8 +252,8 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 }
 
 // The passes of Plan<C>; v ends with the last pass's outputs in registers.
-template <int C, int T, bool SPLIT>
-__device__ __forceinline__ void fft(float2 *v, float *lds, const float2 *__restrict__ src, int a0, int n_spectra,
+template <int C, int T, bool SPLIT, typename Src>
+__device__ __forceinline__ void fft(float2 *v, float *lds, const Src *__restrict__ src, int a0, int n_spectra,
                                     const float2 *__restrict__ tw, int tid) {
     using P = Plan<C>;
     first_pass<C, T, P::R0>(v, src, a0, n_spectra, tid);
@@ -247,6 +265,58 @@ __device__ __forceinline__ void fft(float2 *v, float *lds, const float2 *__restr
         later_pass<C, T, P::R1, P::R0, false>(v, tw, tid);
         exchange<C, T, P::R1, P::R0, P::R2, true, SPLIT>(v, lds, tid, true);
         later_pass<C, T, P::R2, P::R0 * P::R1, true>(v, tw, tid);
+    }
+}
+
+// Real-input spectra (Section 5's 8-bit real samples) from the C-point
+// transform Z of z[n] = x[2n] + j x[2n+1]: with P = Z[(C - k) mod C],
+//   E = (Z[k] + conj P) / 2,  O = (Z[k] - conj P) / 2j,  X[k] = E + W_2C^k O,
+// k < C, W_2C^k = exp(-j pi k / C) = tw2[k].  v holds Z[k] as the last pass
+// left it (k = j + r C/RL of spectrum t, butterfly b = tid + 256 q, (t, j) =
+// (b % T, b / T)) and receives X[k] in the same places.  The partner values
+// travel through LDS in natural [t][k] order, one component at a time when
+// SPLIT.  The LDS may still be read by the last reordering on entry.
+template <int C, int T, int RL, bool SPLIT>
+__device__ __forceinline__ void real_split(float2 *v, float *lds, const float2 *__restrict__ tw2, int tid) {
+    constexpr int Q = kPerThread / RL, CR = C / RL;
+    float pr[kPerThread];                              // partner real parts (SPLIT)
+#pragma unroll
+    for (int comp = 0; comp < (SPLIT ? 2 : 1); ++comp) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int b = tid + kThreads * q;
+            const int t = b % T, j = b / T;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int i = lidx<C>(t, j + r * CR);
+                if constexpr (SPLIT) lds[i] = comp ? v[q * RL + r].y : v[q * RL + r].x;
+                else reinterpret_cast<float2 *>(lds)[i] = v[q * RL + r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int b = tid + kThreads * q;
+            const int t = b % T, j = b / T;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int k = j + r * CR;
+                const int i = lidx<C>(t, (C - k) & (C - 1));
+                if (SPLIT && comp == 0) {
+                    pr[q * RL + r] = lds[i];
+                    continue;
+                }
+                float2 P;
+                if constexpr (SPLIT) P = make_float2(pr[q * RL + r], lds[i]);
+                else P = reinterpret_cast<const float2 *>(lds)[i];
+                const float2 Z = v[q * RL + r];
+                const float2 w = tw2[k];
+                const float er = 0.5f * (Z.x + P.x), ei = 0.5f * (Z.y - P.y);
+                const float orr = 0.5f * (Z.y + P.y), oi = 0.5f * (P.x - Z.x);
+                v[q * RL + r] = make_float2(er + (w.x * orr - w.y * oi), ei + (w.x * oi + w.y * orr));
+            }
+        }
     }
 }
 
@@ -288,11 +358,14 @@ template <> struct Bytes<4> { using T = uint32_t; };
 template <> struct Bytes<8> { using T = uint2; };
 template <> struct Bytes<16> { using T = uint4; };
 
-template <int C, int PREC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC == P_FP32 ? 2 : 3))) void fengine_kernel(
-    const float2 *__restrict__ volts, int64_t ld, int N, int n_spectra, int n_valid_pad,
+// REAL: the input is int8 real samples (ld in bytes, block a at byte a*2C of
+// its row) and tw2 holds exp(-j pi k / C); otherwise complex64 voltages (ld in
+// complex samples, block a at sample a*C) and tw2 is unused.
+template <int C, int PREC, bool REAL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC == P_FP32 || REAL ? 2 : 3))) void fengine_kernel(
+    const void *__restrict__ in, int64_t ld, int N, int n_spectra, int n_valid_pad,
     int n_work, const float *__restrict__ inv_scale,
-    const float2 *__restrict__ tw, uint8_t *__restrict__ spec, int n_tb_cap) {
+    const float2 *__restrict__ tw, const float2 *__restrict__ tw2, uint8_t *__restrict__ spec, int n_tb_cap) {
     using E = typename Elem<PREC>::T;
     constexpr int T = kTC / C;                         // spectra per workgroup
     using P = Plan<C>;
@@ -307,8 +380,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC =
     // reorderings move one component at a time, which halves the buffer so
     // three workgroups share a CU.  FP32, whose wider output staging needs the
     // registers that would allow that, keeps whole complex values (two
-    // workgroups per CU, one round per reordering).
-    constexpr bool SPLIT = PREC != P_FP32;
+    // workgroups per CU, one round per reordering), and so does the
+    // real-input form, whose split step holds both a value and its partner.
+    constexpr bool SPLIT = PREC != P_FP32 && !REAL;
     constexpr int LF = SPLIT ? 1 : 2;                  // floats per LDS element
     constexpr int NPL = 2 * C * S <= T * CP * 4 * LF ? 2 : 1;   // planes staged at a time
     static_assert(NPL * C * S <= T * CP * 4 * LF, "staging must fit the FFT buffer");
@@ -330,7 +404,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC =
     const int a0 = ((rest / N) * GPT + w % GPT) * T;
 
     float2 v[kPerThread];
-    fft<C, T, SPLIT>(v, lds, volts + (int64_t)p * ld, a0, n_spectra, tw, tid);
+    if constexpr (REAL) {
+        const char2 *src = reinterpret_cast<const char2 *>(static_cast<const int8_t *>(in) + (int64_t)p * ld);
+        fft<C, T, SPLIT>(v, lds, src, a0, n_spectra, tw, tid);
+        real_split<C, T, RL, SPLIT>(v, lds, tw2, tid);
+    } else {
+        fft<C, T, SPLIT>(v, lds, static_cast<const float2 *>(in) + (int64_t)p * ld, a0, n_spectra, tw, tid);
+    }
 
     // v[q RL + r] holds channel k = j + r C/RL of spectrum t for last-pass
     // butterfly b = tid + 256 q, (t, j) = (b % T, b / T).  NPL planes at a time
@@ -375,9 +455,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC =
     }
 }
 
-template <int PREC, int C>
-hipError_t launch_c(int N, const float2 *volts, int64_t ld, int n_spectra, const float *inv_scale,
-                    const float2 *tw, void *spec, int n_tb_cap, hipStream_t stream) {
+template <int PREC, int C, bool REAL>
+hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
+                    const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, hipStream_t stream) {
     constexpr int T = kTC / C;
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
@@ -386,26 +466,41 @@ hipError_t launch_c(int N, const float2 *volts, int64_t ld, int n_spectra, const
     const int64_t n_work = (int64_t)N * groups;
     if (n_work <= 0 || n_work > (int64_t)1 << 30) return hipErrorInvalidValue;
     const int grid = (int)((n_work + 7) / 8) * 8;
-    hipLaunchKernelGGL((fengine_kernel<C, PREC>), dim3(grid), dim3(kThreads), 0, stream, volts, ld, N,
-                       n_spectra, n_valid_pad, (int)n_work, inv_scale, tw,
+    hipLaunchKernelGGL((fengine_kernel<C, PREC, REAL>), dim3(grid), dim3(kThreads), 0, stream, in, ld, N,
+                       n_spectra, n_valid_pad, (int)n_work, inv_scale, tw, tw2,
                        static_cast<uint8_t *>(spec), n_tb_cap);
     return hipGetLastError();
 }
 
-template <int PREC>
-hipError_t launch_p(int C, int N, const float2 *volts, int64_t ld, int n_spectra, const float *inv_scale,
-                    const float2 *tw, void *spec, int n_tb_cap, hipStream_t stream) {
+template <int PREC, bool REAL>
+hipError_t launch_p(int C, int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
+                    const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, hipStream_t stream) {
+#define CORR_FENGINE_CASE(c)                                                                            \
+    case c: return launch_c<PREC, c, REAL>(N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
     switch (C) {
-    case 16: return launch_c<PREC, 16>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 32: return launch_c<PREC, 32>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 64: return launch_c<PREC, 64>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 128: return launch_c<PREC, 128>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 256: return launch_c<PREC, 256>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 512: return launch_c<PREC, 512>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 1024: return launch_c<PREC, 1024>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 2048: return launch_c<PREC, 2048>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 4096: return launch_c<PREC, 4096>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
-    case 8192: return launch_c<PREC, 8192>(N, volts, ld, n_spectra, inv_scale, tw, spec, n_tb_cap, stream);
+        CORR_FENGINE_CASE(16)
+        CORR_FENGINE_CASE(32)
+        CORR_FENGINE_CASE(64)
+        CORR_FENGINE_CASE(128)
+        CORR_FENGINE_CASE(256)
+        CORR_FENGINE_CASE(512)
+        CORR_FENGINE_CASE(1024)
+        CORR_FENGINE_CASE(2048)
+        CORR_FENGINE_CASE(4096)
+        CORR_FENGINE_CASE(8192)
+    default: return hipErrorInvalidValue;
+    }
+#undef CORR_FENGINE_CASE
+}
+
+template <bool REAL>
+hipError_t launch_any(int prec, int C, int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
+                      const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, hipStream_t stream) {
+    switch (prec) {
+    case P_FP32: return launch_p<P_FP32, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
+    case P_FP16: return launch_p<P_FP16, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
+    case P_FP8: return launch_p<P_FP8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
+    case P_INT8: return launch_p<P_INT8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -415,13 +510,14 @@ hipError_t launch_p(int C, int N, const float2 *volts, int64_t ld, int n_spectra
 hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld, int n_spectra,
                           const float *inv_scale, const float2 *twiddle, void *spec, int n_tb_cap,
                           hipStream_t stream) {
-    switch (prec) {
-    case P_FP32: return launch_p<P_FP32>(C, N, volts, ld, n_spectra, inv_scale, twiddle, spec, n_tb_cap, stream);
-    case P_FP16: return launch_p<P_FP16>(C, N, volts, ld, n_spectra, inv_scale, twiddle, spec, n_tb_cap, stream);
-    case P_FP8: return launch_p<P_FP8>(C, N, volts, ld, n_spectra, inv_scale, twiddle, spec, n_tb_cap, stream);
-    case P_INT8: return launch_p<P_INT8>(C, N, volts, ld, n_spectra, inv_scale, twiddle, spec, n_tb_cap, stream);
-    default: return hipErrorInvalidValue;
-    }
+    return launch_any<false>(prec, C, N, volts, ld, n_spectra, inv_scale, twiddle, nullptr, spec, n_tb_cap, stream);
+}
+
+hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, int64_t ld, int n_spectra,
+                                const float *inv_scale, const float2 *twiddle, const float2 *twiddle2n, void *spec,
+                                int n_tb_cap, hipStream_t stream) {
+    return launch_any<true>(prec, C, N, samples, ld, n_spectra, inv_scale, twiddle, twiddle2n, spec, n_tb_cap,
+                            stream);
 }
 
 }  // namespace corr

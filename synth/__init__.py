@@ -224,6 +224,97 @@ def int8_spectra(n_spectra: int, n_channels: int, n_inputs: int, seed: int, rms:
 
 
 # --------------------------------------------------------------------------
+# 8-bit real samples (the paper's own test streams, Section 5)
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class RealWorkload:
+    """n_streams streams of 8-bit real samples, transform length 2C (C
+    channels kept), n_integrate spectra.  Each sample is
+    clip(rint(sigma g + a cos(2 pi k0 n / 2C + phi_p)), -128, 127) with g
+    standard normal and phi_p = 2 pi p 3 / n_streams (a phase ramp)."""
+    name: str
+    n_streams: int
+    n_channels: int
+    n_integrate: int
+    seed: int
+    sigma: float = 8.0
+    tone_bin: int = 37
+    tone_amp: float = 6.0
+
+    @property
+    def n_inputs(self) -> int:
+        return self.n_streams
+
+    @property
+    def n_products(self) -> int:
+        return self.n_streams * (self.n_streams + 1) // 2
+
+    @property
+    def cmacs(self) -> int:
+        return self.n_products * self.n_channels * self.n_integrate
+
+
+# The paper's tests: transform length 256 (128 channels kept), 64 to 3072
+# streams, up to 2048 streams on one GPU in its time-division model.
+REAL_WORKLOADS = {
+    f"paper-{n}-r256": RealWorkload(f"paper-{n}-r256", n, 128, 1024, seed=60 + i)
+    for i, n in enumerate((128, 512, 2048, 3072))
+}
+
+
+def small_real(name: str, n_streams: int, n_channels: int, n_integrate: int, seed: int,
+               sigma: float = 8.0, tone_amp: float = 6.0) -> RealWorkload:
+    return RealWorkload(name, n_streams, n_channels, n_integrate, seed, sigma,
+                        tone_bin=37 % n_channels, tone_amp=tone_amp)
+
+
+def _real_tone(w: RealWorkload) -> np.ndarray:
+    """a cos(2 pi k0 n / 2C + phi_p) over one period n < 2C, float64 [N][2C]."""
+    L = 2 * w.n_channels
+    n = np.arange(L, dtype=np.int64)
+    m = (np.int64(w.tone_bin) * n) % L
+    phi = 2 * math.pi * 3.0 * np.arange(w.n_streams, dtype=np.float64) / w.n_streams
+    return w.tone_amp * np.cos(2 * math.pi * m[None, :] / L + phi[:, None])
+
+
+def real8_samples(w: RealWorkload, n_spectra: int | None = None, device: str = "cpu"):
+    """int8 real samples [n_streams][n_spectra * 2C].  'cpu' draws with
+    numpy's PCG64, a torch device with torch's Philox generator (different
+    streams, same distribution), both keyed by the seed."""
+    A = w.n_integrate if n_spectra is None else n_spectra
+    L = 2 * w.n_channels
+    tone = _real_tone(w)
+    if device == "cpu":
+        rng = np.random.default_rng(w.seed)
+        x = rng.standard_normal((w.n_streams, A, L), dtype=np.float32) * np.float32(w.sigma)
+        x += tone[:, None, :].astype(np.float32)
+        return np.clip(np.rint(x), -128, 127).astype(np.int8).reshape(w.n_streams, A * L)
+    import torch
+    dev = torch.device(device)
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(w.seed))
+    out = torch.empty((w.n_streams, A * L), dtype=torch.int8, device=dev)
+    t = torch.as_tensor(tone.astype(np.float32), device=dev)
+    step = max(1, (1 << 27) // max(1, A * L))
+    for p0 in range(0, w.n_streams, step):
+        p1 = min(w.n_streams, p0 + step)
+        x = torch.randn((p1 - p0, A, L), device=dev, generator=g) * w.sigma + t[p0:p1, None, :]
+        out[p0:p1] = torch.clamp(torch.round(x), -128, 127).to(torch.int8).view(p1 - p0, A * L)
+    return out
+
+
+def real8_inv_scale(w: RealWorkload, precision: str) -> np.ndarray:
+    """float32 inv_s[k] mapping the expected per-component RMS of channel k of
+    the length-2C spectrum to the precision's target: noise of variance
+    sigma^2 + 1/12 (the rounding) gives C (sigma^2 + 1/12) per component, the
+    tone adds (a C)^2 / 2 in its channel."""
+    C = w.n_channels
+    var = np.full(C, C * (w.sigma ** 2 + 1.0 / 12.0))
+    var[w.tone_bin] += (w.tone_amp * C) ** 2 / 2.0
+    return (TARGET_RMS[precision] / np.sqrt(var)).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
 # Batched uneven sub-arrays
 # --------------------------------------------------------------------------
 def batched_workloads(n_arrays: int = 64, seed: int = 5, max_channels_log2: int = 12,
