@@ -112,14 +112,36 @@ template <> struct Plan<8192> { static constexpr int NP = 3, R0 = 8, R1 = 32, R2
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
-// Butterfly b of a pass of radix R maps to (spectrum t, index j): (b / (C/R),
-// b % (C/R)), or in the last pass (b % T, b / T) so that neighbouring lanes
-// hold neighbouring spectra of one channel.
-template <int C, int T, int R, bool REMAP>
-__device__ __forceinline__ void bfly_index(int b, int &t, int &j) {
-    if constexpr (REMAP) {
+// Butterfly q of thread tid in a pass of radix R maps to (spectrum t, index
+// j), with b = tid + 256 q:
+//   MAP_PLAIN : (b / (C/R), b % (C/R));
+//   MAP_REMAP : (b % T, b / T), the last pass, so that neighbouring lanes hold
+//               neighbouring spectra of one channel;
+//   MAP_PAIRED: the last pass of the real-input form when C/R >= 2 and the Q
+//               butterflies of a thread are even in number: t = tid % T, and
+//               with g = tid / T, G = 256 / T, butterfly q < Q/2 takes
+//               j = g + G q while butterfly Q-1-q takes its mirror C/R - j (C/R/2
+//               in place of the mirror of j = 0), so a thread holds channel k
+//               and channel C - k of the same spectrum together.
+enum { MAP_PLAIN = 0, MAP_REMAP = 1, MAP_PAIRED = 2 };
+
+template <int C, int T, int R, int MAP>
+__device__ __forceinline__ void bfly_index(int tid, int q, int &t, int &j) {
+    const int b = tid + kThreads * q;
+    if constexpr (MAP == MAP_REMAP) {
         t = b % T;
         j = b / T;
+    } else if constexpr (MAP == MAP_PAIRED) {
+        constexpr int Q = kPerThread / R, CR = C / R, G = kThreads / T;
+        static_assert(T <= kThreads && Q % 2 == 0 && CR == G * Q, "paired mapping needs T | 256 and even Q");
+        t = tid % T;
+        const int g = tid / T;
+        if (q < Q / 2) {
+            j = g + G * q;
+        } else {
+            const int j1 = g + G * (Q - 1 - q);
+            j = j1 ? CR - j1 : CR / 2;
+        }
     } else {
         t = b / (C / R);
         j = b % (C / R);
@@ -149,7 +171,7 @@ __device__ __forceinline__ void first_pass(float2 *v, const Src *__restrict__ sr
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int t, j;
-        bfly_index<C, T, R, false>(tid + kThreads * q, t, j);
+        bfly_index<C, T, R, MAP_PLAIN>(tid, q, t, j);
         float2 *x = v + q * R;
         const bool ok = (a0 + t) < n_spectra;
         const Src *row = src + (int64_t)(ok ? a0 + t : 0) * C + j;
@@ -168,14 +190,14 @@ __device__ __forceinline__ void first_pass(float2 *v, const Src *__restrict__ sr
 // A later pass of radix R after NS points have been combined: butterfly (t, j)
 // (already holding x[t][j + r C/R]) multiplies element r by
 // W_C^(r (j mod NS) C/(NS R)) and does an R-point DFT.
-template <int C, int T, int R, int NS, bool REMAP>
+template <int C, int T, int R, int NS, int MAP>
 __device__ __forceinline__ void later_pass(float2 *v, const float2 *__restrict__ tw, int tid) {
     constexpr int Q = kPerThread / R;
     constexpr int LR = ilog2(R);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int t, j;
-        bfly_index<C, T, R, REMAP>(tid + kThreads * q, t, j);
+        bfly_index<C, T, R, MAP>(tid, q, t, j);
         float2 *x = v + q * R;
         const int m = (j % NS) * (C / (NS * R));
         float2 wp[LR];                                 // W^(m 2^i)
@@ -200,7 +222,7 @@ __device__ __forceinline__ void later_pass(float2 *v, const float2 *__restrict__
 // back taking the registers of one just written (half the LDS, so more
 // workgroups per CU); otherwise whole complex values in one round.
 // wait_first: the LDS may still be read by an earlier exchange.
-template <int C, int T, int R1, int NS1, int R2, bool REMAP2, bool SPLIT>
+template <int C, int T, int R1, int NS1, int R2, int MAP2, bool SPLIT>
 __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wait_first) {
     constexpr int Q1 = kPerThread / R1, Q2 = kPerThread / R2, CR2 = C / R2;
     if constexpr (!SPLIT) {
@@ -209,7 +231,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 #pragma unroll
         for (int q = 0; q < Q1; ++q) {
             int t, j;
-            bfly_index<C, T, R1, false>(tid + kThreads * q, t, j);
+            bfly_index<C, T, R1, MAP_PLAIN>(tid, q, t, j);
             const int base = (j / NS1) * NS1 * R1 + (j % NS1);
 #pragma unroll
             for (int r = 0; r < R1; ++r) l2[lidx<C>(t, base + r * NS1)] = v[q * R1 + r];
@@ -218,7 +240,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 #pragma unroll
         for (int q = 0; q < Q2; ++q) {
             int t, j;
-            bfly_index<C, T, R2, REMAP2>(tid + kThreads * q, t, j);
+            bfly_index<C, T, R2, MAP2>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < R2; ++r) v[q * R2 + r] = l2[lidx<C>(t, j + r * CR2)];
         }
@@ -231,7 +253,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 #pragma unroll
         for (int q = 0; q < Q1; ++q) {
             int t, j;
-            bfly_index<C, T, R1, false>(tid + kThreads * q, t, j);
+            bfly_index<C, T, R1, MAP_PLAIN>(tid, q, t, j);
             const int base = (j / NS1) * NS1 * R1 + (j % NS1);
 #pragma unroll
             for (int r = 0; r < R1; ++r) lds[lidx<C>(t, base + r * NS1)] = comp ? v[q * R1 + r].y : v[q * R1 + r].x;
@@ -240,7 +262,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 #pragma unroll
         for (int q = 0; q < Q2; ++q) {
             int t, j;
-            bfly_index<C, T, R2, REMAP2>(tid + kThreads * q, t, j);
+            bfly_index<C, T, R2, MAP2>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < R2; ++r) {
                 const float e = lds[lidx<C>(t, j + r * CR2)];
@@ -251,25 +273,95 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
     }
 }
 
-// The passes of Plan<C>; v ends with the last pass's outputs in registers.
-template <int C, int T, bool SPLIT, typename Src>
+// Radix, butterflies per thread and index range of the last pass of Plan<C>,
+// and how the real-input form finds the partner Z[C - k] of each Z[k]: in the
+// same thread (MAP_PAIRED, or C/R = 1 where every butterfly has j = 0), else
+// through LDS.
+template <int C> struct Last {
+    using P = Plan<C>;
+    static constexpr int RL = P::NP == 1 ? P::R0 : (P::NP == 2 ? P::R1 : P::R2);
+    static constexpr int Q = kPerThread / RL, CR = C / RL;
+    static constexpr bool PAIRED = CR >= 2 && Q % 2 == 0;
+    static constexpr bool REAL_VIA_LDS = CR >= 2 && Q % 2 == 1;
+};
+
+// The passes of Plan<C>; v ends with the last pass's outputs in registers,
+// laid out by mapping LMAP.
+template <int C, int T, bool SPLIT, int LMAP, typename Src>
 __device__ __forceinline__ void fft(float2 *v, float *lds, const Src *__restrict__ src, int a0, int n_spectra,
                                     const float2 *__restrict__ tw, int tid) {
     using P = Plan<C>;
     first_pass<C, T, P::R0>(v, src, a0, n_spectra, tid);
     if constexpr (P::NP == 2) {
-        exchange<C, T, P::R0, 1, P::R1, true, SPLIT>(v, lds, tid, false);
-        later_pass<C, T, P::R1, P::R0, true>(v, tw, tid);
+        exchange<C, T, P::R0, 1, P::R1, LMAP, SPLIT>(v, lds, tid, false);
+        later_pass<C, T, P::R1, P::R0, LMAP>(v, tw, tid);
     } else if constexpr (P::NP == 3) {
-        exchange<C, T, P::R0, 1, P::R1, false, SPLIT>(v, lds, tid, false);
-        later_pass<C, T, P::R1, P::R0, false>(v, tw, tid);
-        exchange<C, T, P::R1, P::R0, P::R2, true, SPLIT>(v, lds, tid, true);
-        later_pass<C, T, P::R2, P::R0 * P::R1, true>(v, tw, tid);
+        exchange<C, T, P::R0, 1, P::R1, MAP_PLAIN, SPLIT>(v, lds, tid, false);
+        later_pass<C, T, P::R1, P::R0, MAP_PLAIN>(v, tw, tid);
+        exchange<C, T, P::R1, P::R0, P::R2, LMAP, SPLIT>(v, lds, tid, true);
+        later_pass<C, T, P::R2, P::R0 * P::R1, LMAP>(v, tw, tid);
     }
 }
 
-// Real-input spectra (Section 5's 8-bit real samples) from the C-point
-// transform Z of z[n] = x[2n] + j x[2n+1]: with P = Z[(C - k) mod C],
+// X[k] and X[C - k] of the length-2C real-input spectrum from z = Z[k],
+// p = Z[C - k] of the C-point transform of z[n] = x[2n] + j x[2n+1] and
+// w = W_2C^k = exp(-j pi k / C):
+//   E = (z + conj p) / 2,  O = (z - conj p) / 2j,
+//   X[k] = E + w O,  X[C - k] = conj(E - w O)   (W_2C^(C-k) = -conj w).
+__device__ __forceinline__ void split_pair(float2 &z, float2 &p, float2 w) {
+    const float er = 0.5f * (z.x + p.x), ei = 0.5f * (z.y - p.y);
+    const float orr = 0.5f * (z.y + p.y), oi = 0.5f * (p.x - z.x);
+    const float wr = w.x * orr - w.y * oi, wi = w.x * oi + w.y * orr;
+    z = make_float2(er + wr, ei + wi);
+    p = make_float2(er - wr, wi - ei);
+}
+
+// One last-pass butterfly with j = 0: u[r] = Z[r C/RL].  X[0] = Re Z[0] +
+// Im Z[0] (real); X[C/2] = conj Z[C/2]; the others pair r with RL - r.
+template <int C, int RL>
+__device__ __forceinline__ void split_j0(float2 *u, const float2 *__restrict__ tw2) {
+    constexpr int CR = C / RL;
+    u[0] = make_float2(u[0].x + u[0].y, 0.f);
+    if constexpr (RL >= 2) {
+        u[RL / 2] = make_float2(u[RL / 2].x, -u[RL / 2].y);
+#pragma unroll
+        for (int r = 1; r < RL / 2; ++r) split_pair(u[r], u[RL - r], tw2[r * CR]);
+    }
+}
+
+// Real-input split with every partner in the same thread (MAP_PAIRED, or
+// C/R = 1).  In MAP_PAIRED butterfly q < Q/2 (index j) pairs element r with
+// element RL-1-r of butterfly Q-1-q (index C/R - j); the thread with g = 0
+// instead holds j = 0 in butterfly 0 and j = C/R/2 in butterfly Q-1, each
+// paired with itself (r with RL - r, and r with RL-1-r).
+template <int C, int T, int RL>
+__device__ __forceinline__ void real_split_regs(float2 *v, const float2 *__restrict__ tw2, int tid) {
+    constexpr int Q = kPerThread / RL, CR = C / RL;
+    if constexpr (CR == 1) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) split_j0<C, RL>(v + q * RL, tw2);
+    } else {
+        constexpr int G = kThreads / T;
+        const int g = tid / T;
+#pragma unroll
+        for (int q = 0; q < Q / 2; ++q) {
+            float2 *a = v + q * RL, *b = v + (Q - 1 - q) * RL;
+            if (q == 0 && g == 0) {
+                split_j0<C, RL>(a, tw2);
+#pragma unroll
+                for (int r = 0; r < RL / 2; ++r) split_pair(b[r], b[RL - 1 - r], tw2[CR / 2 + r * CR]);
+            } else {
+                const int j = g + G * q;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) split_pair(a[r], b[RL - 1 - r], tw2[j + r * CR]);
+            }
+        }
+    }
+}
+
+// Real-input split through LDS, for last passes whose butterflies per thread
+// are odd in number (a single butterfly, so no pairing within the thread):
+// with P = Z[(C - k) mod C] of the C-point transform Z of z[n] = x[2n] + j x[2n+1],
 //   E = (Z[k] + conj P) / 2,  O = (Z[k] - conj P) / 2j,  X[k] = E + W_2C^k O,
 // k < C, W_2C^k = exp(-j pi k / C) = tw2[k].  v holds Z[k] as the last pass
 // left it (k = j + r C/RL of spectrum t, butterfly b = tid + 256 q, (t, j) =
@@ -277,7 +369,7 @@ __device__ __forceinline__ void fft(float2 *v, float *lds, const Src *__restrict
 // travel through LDS in natural [t][k] order, one component at a time when
 // SPLIT.  The LDS may still be read by the last reordering on entry.
 template <int C, int T, int RL, bool SPLIT>
-__device__ __forceinline__ void real_split(float2 *v, float *lds, const float2 *__restrict__ tw2, int tid) {
+__device__ __forceinline__ void real_split_lds(float2 *v, float *lds, const float2 *__restrict__ tw2, int tid) {
     constexpr int Q = kPerThread / RL, CR = C / RL;
     float pr[kPerThread];                              // partner real parts (SPLIT)
 #pragma unroll
@@ -285,8 +377,8 @@ __device__ __forceinline__ void real_split(float2 *v, float *lds, const float2 *
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int b = tid + kThreads * q;
-            const int t = b % T, j = b / T;
+            int t, j;
+            bfly_index<C, T, RL, MAP_REMAP>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int i = lidx<C>(t, j + r * CR);
@@ -297,8 +389,8 @@ __device__ __forceinline__ void real_split(float2 *v, float *lds, const float2 *
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int b = tid + kThreads * q;
-            const int t = b % T, j = b / T;
+            int t, j;
+            bfly_index<C, T, RL, MAP_REMAP>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int k = j + r * CR;
@@ -362,7 +454,8 @@ template <> struct Bytes<16> { using T = uint4; };
 // its row) and tw2 holds exp(-j pi k / C); otherwise complex64 voltages (ld in
 // complex samples, block a at sample a*C) and tw2 is unused.
 template <int C, int PREC, bool REAL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC == P_FP32 || REAL ? 2 : 3))) void fengine_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    PREC == P_FP32 || (REAL && Last<C>::REAL_VIA_LDS) ? 2 : 3))) void fengine_kernel(
     const void *__restrict__ in, int64_t ld, int N, int n_spectra, int n_valid_pad,
     int n_work, const float *__restrict__ inv_scale,
     const float2 *__restrict__ tw, const float2 *__restrict__ tw2, uint8_t *__restrict__ spec, int n_tb_cap) {
@@ -370,7 +463,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC =
     constexpr int T = kTC / C;                         // spectra per workgroup
     using P = Plan<C>;
     static_assert(P::R0 * P::R1 * P::R2 == C, "radix plan must multiply to C");
-    constexpr int RL = P::NP == 1 ? P::R0 : (P::NP == 2 ? P::R1 : P::R2);   // last radix
+    constexpr int RL = Last<C>::RL;                    // last radix
+    constexpr int LMAP = REAL && Last<C>::PAIRED ? MAP_PAIRED : MAP_REMAP;
     constexpr int CP = C + (C >> P::SH) + P::EX;       // LDS row stride (floats)
     constexpr int ES = (int)sizeof(E);
     constexpr int TB = kRowBytes / ES;                 // spectra per time block
@@ -381,8 +475,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC =
     // three workgroups share a CU.  FP32, whose wider output staging needs the
     // registers that would allow that, keeps whole complex values (two
     // workgroups per CU, one round per reordering), and so does the
-    // real-input form, whose split step holds both a value and its partner.
-    constexpr bool SPLIT = PREC != P_FP32 && !REAL;
+    // real-input form where the partners of its split step come through LDS.
+    constexpr bool SPLIT = PREC != P_FP32 && !(REAL && Last<C>::REAL_VIA_LDS);
     constexpr int LF = SPLIT ? 1 : 2;                  // floats per LDS element
     constexpr int NPL = 2 * C * S <= T * CP * 4 * LF ? 2 : 1;   // planes staged at a time
     static_assert(NPL * C * S <= T * CP * 4 * LF, "staging must fit the FFT buffer");
@@ -406,14 +500,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC =
     float2 v[kPerThread];
     if constexpr (REAL) {
         const char2 *src = reinterpret_cast<const char2 *>(static_cast<const int8_t *>(in) + (int64_t)p * ld);
-        fft<C, T, SPLIT>(v, lds, src, a0, n_spectra, tw, tid);
-        real_split<C, T, RL, SPLIT>(v, lds, tw2, tid);
+        fft<C, T, SPLIT, LMAP>(v, lds, src, a0, n_spectra, tw, tid);
+        if constexpr (Last<C>::REAL_VIA_LDS) real_split_lds<C, T, RL, SPLIT>(v, lds, tw2, tid);
+        else real_split_regs<C, T, RL>(v, tw2, tid);
     } else {
-        fft<C, T, SPLIT>(v, lds, static_cast<const float2 *>(in) + (int64_t)p * ld, a0, n_spectra, tw, tid);
+        fft<C, T, SPLIT, LMAP>(v, lds, static_cast<const float2 *>(in) + (int64_t)p * ld, a0, n_spectra, tw, tid);
     }
 
     // v[q RL + r] holds channel k = j + r C/RL of spectrum t for last-pass
-    // butterfly b = tid + 256 q, (t, j) = (b % T, b / T).  NPL planes at a time
+    // butterfly q, (t, j) as mapping LMAP gives them.  NPL planes at a time
     // are requantised and staged in LDS as [plane][channel][spectrum], then
     // stored as runs of consecutive spectra of each (channel, plane) row.
     // Destination: spec[k][tb][p][plane][TB].
@@ -428,8 +523,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PREC =
         __syncthreads();                               // every thread is done reading lds
 #pragma unroll
         for (int q = 0; q < kPerThread / RL; ++q) {
-            const int b = tid + kThreads * q;
-            const int t = b % T, j = b / T;
+            int t, j;
+            bfly_index<C, T, RL, LMAP>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int k = j + r * CR;
