@@ -34,6 +34,7 @@ struct corr_ctx {
     size_t acc_bytes = 0;
     float2 *twiddle = nullptr;
     float2 *twiddle2n = nullptr;       // exp(-j pi k / C), k < C (real-input F-engine)
+    float *unit_scale = nullptr;       // C ones: the F-engine's scale when the caller gives none
     float *scale2 = nullptr;          // s_k^2 of the F-engine's spectra
     float *scale2_user = nullptr;     // s_k^2 of caller spectra
     void *dump_tmp = nullptr;         // staging for converted dumps to host
@@ -295,6 +296,7 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
         return cleanup_fail(e == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP, "hipMalloc accumulators failed");
     if ((e = hipMalloc(&h->twiddle, (size_t)C * sizeof(float2))) != hipSuccess ||
         (e = hipMalloc(&h->twiddle2n, (size_t)C * sizeof(float2))) != hipSuccess ||
+        (e = hipMalloc(&h->unit_scale, (size_t)C * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&h->scale2, (size_t)C * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&h->scale2_user, (size_t)C * sizeof(float))) != hipSuccess)
         return cleanup_fail(CORR_E_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -310,7 +312,9 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
         tw2[m] = make_float2((float)std::cos(ang2), (float)-std::sin(ang2));
     }
     if ((e = hipMemcpy(h->twiddle, tw.data(), (size_t)C * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(h->twiddle2n, tw2.data(), (size_t)C * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+        (e = hipMemcpy(h->twiddle2n, tw2.data(), (size_t)C * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->unit_scale, std::vector<float>(C, 1.0f).data(), (size_t)C * sizeof(float),
+                       hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup_fail(CORR_E_HIP, std::string("hipMemcpy twiddles: ") + hipGetErrorString(e));
     *out = h;
     return CORR_OK;
@@ -324,6 +328,7 @@ static void destroy_ctx(corr_ctx *h) {
     (void)hipFree(h->acc);
     (void)hipFree(h->twiddle);
     (void)hipFree(h->twiddle2n);
+    (void)hipFree(h->unit_scale);
     (void)hipFree(h->scale2);
     (void)hipFree(h->scale2_user);
     (void)hipFree(h->dump_tmp);
@@ -355,7 +360,7 @@ corr_status corr_fengine(corr_handle h, const void *d_volts, int64_t ld_samples,
     hipError_t e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
     e = launch_fengine(h->prec, h->C, h->N, static_cast<const float2 *>(d_volts), ld_samples, n_spectra,
-                       d_inv_scale, h->twiddle, h->spec, h->n_tb_cap, h->stream);
+                       d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->spec, h->n_tb_cap, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine launch");
     h->n_held = n_spectra;
     h->held_from_fengine = true;
@@ -379,8 +384,9 @@ corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, int64_t l
 
     hipError_t e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
-    e = launch_fengine_real8(h->prec, h->C, h->N, d_samples, ld_samples, n_spectra, d_inv_scale, h->twiddle,
-                             h->twiddle2n, h->spec, h->n_tb_cap, h->stream);
+    e = launch_fengine_real8(h->prec, h->C, h->N, d_samples, ld_samples, n_spectra,
+                             d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->twiddle2n, h->spec,
+                             h->n_tb_cap, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine_real8 launch");
     h->n_held = n_spectra;
     h->held_from_fengine = true;

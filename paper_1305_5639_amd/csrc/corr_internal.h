@@ -48,7 +48,7 @@ inline int time_block(int prec) { return kRowBytes / elem_bytes(prec); }
 
 // F-engine: C-point FFTs of n_spectra blocks per input, requantised into the
 // time-blocked planar spectra buffer.  Spectra in [n_spectra, n_tb*TB) of the
-// last block are written as zeros.
+// last block are written as zeros.  inv_scale: C floats, never null.
 hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld,
                           int n_spectra, const float *inv_scale, const float2 *twiddle,
                           void *spec, int n_tb_cap, hipStream_t stream);
