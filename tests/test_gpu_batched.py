@@ -144,3 +144,26 @@ def test_batched_graph_replay_matches_eager():
                 assert np.array_equal(got[i], ref[i]), (rep, i)
             torch.zeros(1000, device=DEV).sum().item()       # unrelated eager work between replays
         b.close()
+
+
+def test_batched_real_input_sub_arrays_int8_exact():
+    """Sub-arrays fed by the real-input F-engine (8-bit real samples): the
+    batched X-engine is exact against the integer oracle on each sub-array's
+    spectra, and those spectra are the requantised float64 DFT of length 2C."""
+    shapes = [(24, 1, 128, 130), (7, 1, 64, 64), (70, 1, 256, 40)]
+    say("batched int8 on real-input sub-arrays")
+    with corr.Batch(shapes, "int8") as b:
+        xs, invs = [], []
+        for i, (st, _, C, A) in enumerate(shapes):
+            rw = synth.small_real(f"b-r8-{i}", st, C, A, seed=80 + i)
+            xs.append(synth.real8_samples(rw))
+            invs.append(synth.real8_inv_scale(rw, "int8"))
+            b.subs[i].fengine_real8(torch.from_numpy(xs[i]).to(DEV), A, torch.from_numpy(invs[i]).to(DEV))
+        b.xengine([A for (_, _, _, A) in shapes])
+        for i, (st, _, C, A) in enumerate(shapes):
+            sp = b.subs[i].spectra().cpu().numpy()
+            got = b.subs[i].dump().cpu().numpy().astype(np.int64)
+            assert np.array_equal(got, oracle.xengine_i8(spectra_akp_to_apk(sp))), i
+            y = oracle.fengine_real8(xs[i], C, A) * invs[i].astype(np.float64)[None, None, :]
+            q = spectra_akp_to_apk(sp).astype(np.float64)
+            assert max(np.max(np.abs(q[..., 0] - y.real)), np.max(np.abs(q[..., 1] - y.imag))) <= 0.5 + 1e-3, i
