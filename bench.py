@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-sub-array batched (persistent, graph-captured) section")
+    ap.add_argument("--batched-blocks-per-x", type=int, default=4,
+                    help="F-engine time blocks appended per batched X-engine launch")
     ap.add_argument("--batched-steps", type=int, default=8,
                     help="graph replays per integration in the batched section")
     ap.add_argument("--cpu-channels", type=int, default=768)
@@ -397,18 +399,23 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count()}
 
 
-def run_batched(torch, corr, synth, steps_per_integration, reps=3):
+def run_batched(torch, corr, synth, steps_per_integration, blocks_per_x=4, reps=3):
     """64 uneven sub-arrays, FP16 in / FP32 accumulate.  Each sub-array's
-    integration A_s is processed in `steps_per_integration` time blocks of
-    ceil(A_s / steps) spectra; one time block of every sub-array is one graph
-    replay: 64 F-engine launches, then ONE persistent X-engine launch.
-    Reports the X-engine as one batched launch vs 64 per-array launches (same
-    tuned block sizes), and the graph-replayed F + X step."""
+    integration A_s is channelised in `steps_per_integration` time blocks of
+    n_s = ceil(A_s / steps) spectra (rounded up to whole 32-spectrum time
+    blocks), appended into its held spectra; every `blocks_per_x` blocks ONE
+    persistent X-engine launch correlates all sub-arrays' held spectra, so the
+    accumulators are read and written steps / blocks_per_x times per
+    integration.  One graph replay = blocks_per_x x 64 F-engine launches + the
+    batched X-engine.  Reports the X-engine as one batched launch vs 64
+    per-array launches (same tuned block sizes), and the graph-replayed step."""
     prec = "fp16"
+    tb = 32
     ws = synth.batched_workloads()
-    ns = [-(-w.n_integrate // steps_per_integration) for w in ws]
-    shapes = [(w.n_stations, w.n_pols, w.n_channels, n) for w, n in zip(ws, ns)]
-    cm_step = sum(w.n_products * w.n_channels * n for w, n in zip(ws, ns))
+    ns = [-(-(-(-w.n_integrate // steps_per_integration)) // tb) * tb for w in ws]
+    held = [blocks_per_x * n for n in ns]
+    shapes = [(w.n_stations, w.n_pols, w.n_channels, h) for w, h in zip(ws, held)]
+    cm_step = sum(w.n_products * w.n_channels * h for w, h in zip(ws, held))
     stream = torch.cuda.Stream()
     out = {}
     with torch.cuda.stream(stream):
@@ -417,12 +424,17 @@ def run_batched(torch, corr, synth, steps_per_integration, reps=3):
             volts.append(synth.voltages(w, n_spectra=n, device="cuda"))
             invs.append(torch.from_numpy(synth.inv_scale(w, prec)).to("cuda"))
         b = corr.Batch(shapes, prec, stream=stream)
+
+        def f_blocks():
+            for blk in range(blocks_per_x):
+                for i, sub in enumerate(b.subs):
+                    sub.fengine(volts[i], ns[i], invs[i], first_spectrum=blk * ns[i])
+
         t0 = time.perf_counter()
-        for i, sub in enumerate(b.subs):
-            sub.fengine(volts[i], ns[i], invs[i])
-        tiles = [sub.autotune(n) for sub, n in zip(b.subs, ns)]
+        f_blocks()
+        tiles = [sub.autotune(h) for sub, h in zip(b.subs, held)]
         tune_s = time.perf_counter() - t0
-        b.xengine(ns)                                          # warm-up; fixes the work list
+        b.xengine(held)                                        # warm-up; fixes the work list
         stream.synchronize()
 
         def timed(fn, k):
@@ -435,19 +447,19 @@ def run_batched(torch, corr, synth, steps_per_integration, reps=3):
             return e0.elapsed_time(e1) / k
 
         def per_array():
-            for sub, n in zip(b.subs, ns):
-                sub.xengine(n)
+            for sub, h in zip(b.subs, held):
+                sub.xengine(h)
 
         per_array()
         t_per = timed(per_array, reps)
-        t_bat = timed(lambda: b.xengine(ns), reps)
+        t_bat = timed(lambda: b.xengine(held), reps)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
-            for i, sub in enumerate(b.subs):
-                sub.fengine(volts[i], ns[i], invs[i])
-            b.xengine(ns)
+            f_blocks()
+            b.xengine(held)
         g.replay()
-        t_step = timed(g.replay, steps_per_integration)
+        replays = max(1, steps_per_integration // blocks_per_x)
+        t_step = timed(g.replay, replays)
         stream.synchronize()
         b.close()
         del volts, invs
@@ -456,8 +468,9 @@ def run_batched(torch, corr, synth, steps_per_integration, reps=3):
         "workload": "batched-64: 64 sub-arrays, stations log-uniform 16..512 x 2 pols, "
                     "channels 2^(8..12), integration 256..2048 (seed 5), FP16 in / FP32 accumulate",
         "n_subarrays": len(ws),
+        "spectra_per_fengine_block": ns,
+        "fengine_blocks_per_xengine": blocks_per_x,
         "cmac_per_step": cm_step,
-        "spectra_per_step": ns,
         "tiles": tiles,
         "autotune_s": tune_s,
         "xengine_batched_ms": t_bat,
@@ -467,8 +480,8 @@ def run_batched(torch, corr, synth, steps_per_integration, reps=3):
         "batched_speedup_vs_per_array": t_per / t_bat,
         "graph_step_ms": t_step,
         "graph_step_tcmacs": cm_step / (t_step * 1e-3) / 1e12,
-        "integration_ms": t_step * steps_per_integration,
-        "steps_per_integration": steps_per_integration,
+        "integration_ms": t_step * replays,
+        "graph_steps_per_integration": replays,
     }
     return out
 
@@ -556,9 +569,10 @@ def main():
     batched = None
     if not args.no_batched:
         log("batched: 64 uneven sub-arrays")
-        batched = run_batched(torch, corr, synth, args.batched_steps)
+        batched = run_batched(torch, corr, synth, args.batched_steps, args.batched_blocks_per_x)
         log(f"batched: X {batched['xengine_batched_ms']:.3f} ms (one launch) vs "
-            f"{batched['xengine_per_array_ms']:.3f} ms (64 launches); graph step {batched['graph_step_ms']:.3f} ms")
+            f"{batched['xengine_per_array_ms']:.3f} ms (64 launches); graph step {batched['graph_step_ms']:.3f} ms; "
+            f"integration {batched['integration_ms']:.1f} ms")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -165,6 +165,31 @@ CORR_API corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, 
                                         int32_t n_spectra, const float *d_inv_scale);
 
 /*
+ * The same two F-engines writing at an offset of the held spectra, so that an
+ * integration (Eq. 2) longer than one batch of samples can be channelised in
+ * pieces and correlated by one corr_xengine call, which reads and writes the
+ * accumulators once instead of once per piece.
+ *   first_spectrum : where the n_spectra new spectra go in the held set.  A
+ *                    multiple of the time block (16 spectra for CORR_FP32, 32
+ *                    for CORR_FP16, 64 for CORR_FP8_E4M3 and CORR_INT8);
+ *                    first_spectrum + n_spectra <= n_integrate.  0 is the
+ *                    plain call.  Above 0 the held spectra must come from an
+ *                    F-engine and reach first_spectrum (no gap), else
+ *                    CORR_E_STATE.  Afterwards the held set is
+ *                    [0, first_spectrum + n_spectra).
+ * Every piece of one held set must use the same d_inv_scale: the X-engine
+ * rescales all held spectra with the last call's s_k^2.
+ * The other arguments are as for corr_fengine / corr_fengine_real8; the data
+ * read are samples [0, n_spectra*C) (resp. 2C) of each row of this call's
+ * buffer.
+ */
+CORR_API corr_status corr_fengine_at(corr_handle h, const void *d_volts, int64_t ld_samples,
+                                     int32_t n_spectra, const float *d_inv_scale, int32_t first_spectrum);
+CORR_API corr_status corr_fengine_real8_at(corr_handle h, const int8_t *d_samples, int64_t ld_samples,
+                                           int32_t n_spectra, const float *d_inv_scale,
+                                           int32_t first_spectrum);
+
+/*
  * X-engine (Eq. 2): add n_spectra spectra into the accumulators.
  *   d_spectra   : NULL = the first n_spectra spectra of the last corr_fengine
  *                 (n_spectra above that call's count is CORR_E_STATE); else

@@ -44,6 +44,7 @@ ABI_FUNCTIONS = (
     "corr_copy_spectra", "corr_get_counts", "corr_status_string", "corr_last_error",
     "corr_set_tile", "corr_autotune", "corr_create_batched", "corr_batch_get",
     "corr_xengine_batched", "corr_destroy_batched", "corr_xengine_rect", "corr_fengine_real8",
+    "corr_fengine_at", "corr_fengine_real8_at",
 )
 
 
@@ -90,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.corr_destroy.argtypes = [P]
         L.corr_fengine.argtypes = [P, P, i64, i32, P]
         L.corr_fengine_real8.argtypes = [P, P, i64, i32, P]
+        L.corr_fengine_at.argtypes = [P, P, i64, i32, P, i32]
+        L.corr_fengine_real8_at.argtypes = [P, P, i64, i32, P, i32]
         L.corr_xengine.argtypes = [P, P, i32, P]
         L.corr_dump_visibilities.argtypes = [P, P, i32, i32]
         L.corr_copy_spectra.argtypes = [P, P, i32]
@@ -105,7 +108,8 @@ def lib() -> ctypes.CDLL:
         L.corr_xengine_batched.argtypes = [P, ctypes.POINTER(i32)]
         L.corr_destroy_batched.argtypes = [P]
         L.corr_xengine_rect.argtypes = [P, i32, i32, i32, i32, i32, P, i32]
-        for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_fengine_real8", "corr_xengine",
+        for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_fengine_real8", "corr_fengine_at",
+                  "corr_fengine_real8_at", "corr_xengine",
                   "corr_xengine_rect",
                   "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts", "corr_set_tile",
                   "corr_autotune", "corr_create_batched", "corr_batch_get", "corr_xengine_batched",
@@ -194,20 +198,30 @@ def corr_destroy(h) -> None:
     _check(lib().corr_destroy(h), "corr_destroy", h)
 
 
-def corr_fengine(h, volts, n_spectra: int, inv_scale=None, ld_samples: int | None = None) -> None:
+def corr_fengine(h, volts, n_spectra: int, inv_scale=None, ld_samples: int | None = None,
+                 first_spectrum: int = 0) -> None:
     if ld_samples is None:
         ld_samples = volts.shape[-1]
-    _check(lib().corr_fengine(h, _ptr(volts), int(ld_samples), int(n_spectra), _ptr(inv_scale)),
-           "corr_fengine", h)
+    if first_spectrum:
+        _check(lib().corr_fengine_at(h, _ptr(volts), int(ld_samples), int(n_spectra), _ptr(inv_scale),
+                                     int(first_spectrum)), "corr_fengine_at", h)
+    else:
+        _check(lib().corr_fengine(h, _ptr(volts), int(ld_samples), int(n_spectra), _ptr(inv_scale)),
+               "corr_fengine", h)
 
 
-def corr_fengine_real8(h, samples, n_spectra: int, inv_scale=None, ld_samples: int | None = None) -> None:
+def corr_fengine_real8(h, samples, n_spectra: int, inv_scale=None, ld_samples: int | None = None,
+                       first_spectrum: int = 0) -> None:
     """samples: int8 [n_inputs][ld] real samples (device); spectrum a of row p
     is the length-2C DFT of samples [a*2C, (a+1)*2C), channels 0..C-1."""
     if ld_samples is None:
         ld_samples = samples.shape[-1]
-    _check(lib().corr_fengine_real8(h, _ptr(samples), int(ld_samples), int(n_spectra), _ptr(inv_scale)),
-           "corr_fengine_real8", h)
+    if first_spectrum:
+        _check(lib().corr_fengine_real8_at(h, _ptr(samples), int(ld_samples), int(n_spectra), _ptr(inv_scale),
+                                           int(first_spectrum)), "corr_fengine_real8_at", h)
+    else:
+        _check(lib().corr_fengine_real8(h, _ptr(samples), int(ld_samples), int(n_spectra), _ptr(inv_scale)),
+               "corr_fengine_real8", h)
 
 
 def corr_xengine(h, spectra, n_spectra: int, inv_scale=None) -> None:
@@ -284,11 +298,13 @@ class Correlator:
         self._owned = _borrowed is None
         self.handle = corr_create(self.params, stream) if self._owned else _borrowed
 
-    def fengine(self, volts, n_spectra, inv_scale=None, ld_samples=None):
-        corr_fengine(self.handle, volts, n_spectra, inv_scale, ld_samples)
+    def fengine(self, volts, n_spectra, inv_scale=None, ld_samples=None, first_spectrum=0):
+        """F-engine into the held spectra; first_spectrum > 0 appends at that
+        (time-block aligned) offset."""
+        corr_fengine(self.handle, volts, n_spectra, inv_scale, ld_samples, first_spectrum)
 
-    def fengine_real8(self, samples, n_spectra, inv_scale=None, ld_samples=None):
-        corr_fengine_real8(self.handle, samples, n_spectra, inv_scale, ld_samples)
+    def fengine_real8(self, samples, n_spectra, inv_scale=None, ld_samples=None, first_spectrum=0):
+        corr_fengine_real8(self.handle, samples, n_spectra, inv_scale, ld_samples, first_spectrum)
 
     def xengine(self, n_spectra, spectra=None, inv_scale=None):
         corr_xengine(self.handle, spectra, n_spectra, inv_scale)

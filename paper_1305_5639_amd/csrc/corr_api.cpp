@@ -344,14 +344,32 @@ corr_status corr_destroy(corr_handle h) {
     return CORR_OK;
 }
 
-corr_status corr_fengine(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
-                         const float *d_inv_scale) {
+}  // extern "C"
+
+// Placement checks shared by the F-engine entry points: spectra
+// [first, first + n) of the held set, first a whole number of time blocks and
+// no gap after the spectra already held.
+static corr_status check_placement(corr_ctx *h, int32_t first, int32_t n_spectra) {
+    if (first < 0) return fail(h, CORR_E_INVALID_ARG, "first_spectrum must be >= 0");
+    if (first % time_block(h->prec))
+        return fail(h, CORR_E_INVALID_ARG, "first_spectrum must be a multiple of the time block");
+    if (n_spectra < 1 || (int64_t)first + n_spectra > h->p.n_integrate)
+        return fail(h, CORR_E_INVALID_ARG, "need 1 <= n_spectra and first_spectrum + n_spectra <= n_integrate");
+    if (first > 0 && (!h->held_from_fengine || first > h->n_held))
+        return fail(h, CORR_E_STATE, "appending needs F-engine spectra held up to first_spectrum");
+    return CORR_OK;
+}
+
+extern "C" {
+
+corr_status corr_fengine_at(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
+                            const float *d_inv_scale, int32_t first_spectrum) {
     if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
     if (!d_volts) return fail(h, CORR_E_INVALID_ARG, "d_volts is NULL");
     if (!aligned(d_volts, 8)) return fail(h, CORR_E_INVALID_ARG, "d_volts must be 8-byte aligned");
     if (d_inv_scale && !aligned(d_inv_scale, 4)) return fail(h, CORR_E_INVALID_ARG, "d_inv_scale misaligned");
-    if (n_spectra < 1 || n_spectra > h->p.n_integrate)
-        return fail(h, CORR_E_INVALID_ARG, "n_spectra must be in 1..n_integrate");
+    corr_status st = check_placement(h, first_spectrum, n_spectra);
+    if (st != CORR_OK) return st;
     if (ld_samples < (int64_t)n_spectra * h->C)
         return fail(h, CORR_E_INVALID_ARG, "ld_samples < n_spectra * n_channels");
     if (h->prec == P_INT8 && !d_inv_scale)
@@ -360,23 +378,29 @@ corr_status corr_fengine(corr_handle h, const void *d_volts, int64_t ld_samples,
     hipError_t e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
     e = launch_fengine(h->prec, h->C, h->N, static_cast<const float2 *>(d_volts), ld_samples, n_spectra,
-                       d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->spec, h->n_tb_cap, h->stream);
+                       d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->spec, h->n_tb_cap,
+                       first_spectrum / time_block(h->prec), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine launch");
-    h->n_held = n_spectra;
+    h->n_held = first_spectrum + n_spectra;
     h->held_from_fengine = true;
     h->err.clear();
     return CORR_OK;
 }
 
-corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, int64_t ld_samples, int32_t n_spectra,
-                               const float *d_inv_scale) {
+corr_status corr_fengine(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
+                         const float *d_inv_scale) {
+    return corr_fengine_at(h, d_volts, ld_samples, n_spectra, d_inv_scale, 0);
+}
+
+corr_status corr_fengine_real8_at(corr_handle h, const int8_t *d_samples, int64_t ld_samples, int32_t n_spectra,
+                                  const float *d_inv_scale, int32_t first_spectrum) {
     if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
     if (!d_samples) return fail(h, CORR_E_INVALID_ARG, "d_samples is NULL");
     if (!aligned(d_samples, 2)) return fail(h, CORR_E_INVALID_ARG, "d_samples must be 2-byte aligned");
     if (ld_samples % 2) return fail(h, CORR_E_INVALID_ARG, "ld_samples must be even");
     if (d_inv_scale && !aligned(d_inv_scale, 4)) return fail(h, CORR_E_INVALID_ARG, "d_inv_scale misaligned");
-    if (n_spectra < 1 || n_spectra > h->p.n_integrate)
-        return fail(h, CORR_E_INVALID_ARG, "n_spectra must be in 1..n_integrate");
+    corr_status st = check_placement(h, first_spectrum, n_spectra);
+    if (st != CORR_OK) return st;
     if (ld_samples < (int64_t)n_spectra * 2 * h->C)
         return fail(h, CORR_E_INVALID_ARG, "ld_samples < n_spectra * 2 * n_channels");
     if (h->prec == P_INT8 && !d_inv_scale)
@@ -386,12 +410,17 @@ corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, int64_t l
     if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
     e = launch_fengine_real8(h->prec, h->C, h->N, d_samples, ld_samples, n_spectra,
                              d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->twiddle2n, h->spec,
-                             h->n_tb_cap, h->stream);
+                             h->n_tb_cap, first_spectrum / time_block(h->prec), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine_real8 launch");
-    h->n_held = n_spectra;
+    h->n_held = first_spectrum + n_spectra;
     h->held_from_fengine = true;
     h->err.clear();
     return CORR_OK;
+}
+
+corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, int64_t ld_samples, int32_t n_spectra,
+                               const float *d_inv_scale) {
+    return corr_fengine_real8_at(h, d_samples, ld_samples, n_spectra, d_inv_scale, 0);
 }
 
 corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra, const float *d_inv_scale) {

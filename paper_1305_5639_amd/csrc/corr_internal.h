@@ -48,17 +48,18 @@ inline int time_block(int prec) { return kRowBytes / elem_bytes(prec); }
 
 // F-engine: C-point FFTs of n_spectra blocks per input, requantised into the
 // time-blocked planar spectra buffer.  Spectra in [n_spectra, n_tb*TB) of the
-// last block are written as zeros.  inv_scale: C floats, never null.
+// last block are written as zeros.  inv_scale: C floats, never null.  The
+// spectra land from time block first_tb of the buffer on.
 hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld,
                           int n_spectra, const float *inv_scale, const float2 *twiddle,
-                          void *spec, int n_tb_cap, hipStream_t stream);
+                          void *spec, int n_tb_cap, int first_tb, hipStream_t stream);
 
 // F-engine on int8 real samples (Section 5): block a of row p is the 2C bytes
 // samples[p*ld + a*2C ..]; channels k < C of its length-2C DFT.  twiddle2n[k]
 // = exp(-j pi k / C), k < C.  ld even.
 hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, int64_t ld, int n_spectra,
                                 const float *inv_scale, const float2 *twiddle, const float2 *twiddle2n,
-                                void *spec, int n_tb_cap, hipStream_t stream);
+                                void *spec, int n_tb_cap, int first_tb, hipStream_t stream);
 
 // X-engine: accumulate Eq. 2 over the first n_spectra spectra of the spectra
 // buffer into acc (spectra past n_spectra in the last time block are masked to

@@ -476,7 +476,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     PREC == P_FP32 || (REAL && Last<C>::REAL_VIA_LDS) ? 2 : 3))) void fengine_kernel(
     const void *__restrict__ in, int64_t ld, int N, int n_spectra, int n_valid_pad,
     int n_work, const float *__restrict__ inv_scale,
-    const float2 *__restrict__ tw, const float2 *__restrict__ tw2, uint8_t *__restrict__ spec, int n_tb_cap) {
+    const float2 *__restrict__ tw, const float2 *__restrict__ tw2, uint8_t *__restrict__ spec, int n_tb_cap,
+    int tb0) {
     using E = typename Elem<PREC>::T;
     constexpr int T = kTC / C;                         // spectra per workgroup
     using P = Plan<C>;
@@ -576,7 +577,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
             const int pl = pl0 + row / C, k = row % C;
             const int a = a0 + x * (CH / ES);
             if (a >= n_valid_pad) continue;
-            const int tb = a / TB, within = a % TB;
+            const int tb = tb0 + a / TB, within = a % TB;
             uint8_t *dst = spec + (int64_t)k * k_stride + ((int64_t)tb * N + p) * (2 * kRowBytes) +
                            pl * kRowBytes + within * ES;
             *reinterpret_cast<V *>(dst) = *reinterpret_cast<const V *>(stage + c * CH);
@@ -586,7 +587,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 
 template <int PREC, int C, bool REAL>
 hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                    const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, hipStream_t stream) {
+                    const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, int tb0, hipStream_t stream) {
     constexpr int T = kTC / C;
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
@@ -597,15 +598,15 @@ hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const floa
     const int grid = (int)((n_work + 7) / 8) * 8;
     hipLaunchKernelGGL((fengine_kernel<C, PREC, REAL>), dim3(grid), dim3(kThreads), 0, stream, in, ld, N,
                        n_spectra, n_valid_pad, (int)n_work, inv_scale, tw, tw2,
-                       static_cast<uint8_t *>(spec), n_tb_cap);
+                       static_cast<uint8_t *>(spec), n_tb_cap, tb0);
     return hipGetLastError();
 }
 
 template <int PREC, bool REAL>
 hipError_t launch_p(int C, int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                    const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, hipStream_t stream) {
+                    const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, int tb0, hipStream_t stream) {
 #define CORR_FENGINE_CASE(c)                                                                            \
-    case c: return launch_c<PREC, c, REAL>(N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
+    case c: return launch_c<PREC, c, REAL>(N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
     switch (C) {
         CORR_FENGINE_CASE(16)
         CORR_FENGINE_CASE(32)
@@ -624,12 +625,12 @@ hipError_t launch_p(int C, int N, const void *in, int64_t ld, int n_spectra, con
 
 template <bool REAL>
 hipError_t launch_any(int prec, int C, int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                      const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, hipStream_t stream) {
+                      const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, int tb0, hipStream_t stream) {
     switch (prec) {
-    case P_FP32: return launch_p<P_FP32, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
-    case P_FP16: return launch_p<P_FP16, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
-    case P_FP8: return launch_p<P_FP8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
-    case P_INT8: return launch_p<P_INT8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, stream);
+    case P_FP32: return launch_p<P_FP32, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
+    case P_FP16: return launch_p<P_FP16, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
+    case P_FP8: return launch_p<P_FP8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
+    case P_INT8: return launch_p<P_INT8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -637,16 +638,17 @@ hipError_t launch_any(int prec, int C, int N, const void *in, int64_t ld, int n_
 }  // namespace
 
 hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld, int n_spectra,
-                          const float *inv_scale, const float2 *twiddle, void *spec, int n_tb_cap,
+                          const float *inv_scale, const float2 *twiddle, void *spec, int n_tb_cap, int first_tb,
                           hipStream_t stream) {
-    return launch_any<false>(prec, C, N, volts, ld, n_spectra, inv_scale, twiddle, nullptr, spec, n_tb_cap, stream);
+    return launch_any<false>(prec, C, N, volts, ld, n_spectra, inv_scale, twiddle, nullptr, spec, n_tb_cap, first_tb,
+                             stream);
 }
 
 hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, int64_t ld, int n_spectra,
                                 const float *inv_scale, const float2 *twiddle, const float2 *twiddle2n, void *spec,
-                                int n_tb_cap, hipStream_t stream) {
+                                int n_tb_cap, int first_tb, hipStream_t stream) {
     return launch_any<true>(prec, C, N, samples, ld, n_spectra, inv_scale, twiddle, twiddle2n, spec, n_tb_cap,
-                            stream);
+                            first_tb, stream);
 }
 
 }  // namespace corr
