@@ -93,3 +93,34 @@ def test_placement_rules():
         c.xengine(32, torch.zeros((32, C, N, 2), dtype=torch.float16, device=DEV))
         with pytest.raises(corr.CorrError):
             c.fengine(v, 32, first_spectrum=32)
+
+
+def test_graph_replay_of_real_input_pieces_and_xengine():
+    """Real-input F-engine pieces and the X-engine of one handle captured in a
+    HIP graph right after a reset (so the captured X-engine writes the
+    accumulators): every replay, with eager work between, equals the eager
+    integration, bit for bit (int8)."""
+    N, C, A = 20, 128, 256
+    say(f"graph replay real8 pieces N={N} C={C} A={A}")
+    rw = synth.small_real("ap-g", N, C, A, seed=92)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        xd = torch.from_numpy(synth.real8_samples(rw)).to(DEV)
+        inv = torch.from_numpy(synth.real8_inv_scale(rw, "int8")).to(DEV)
+        pieces = [(f, n, xd[:, f * 2 * C:(f + n) * 2 * C].contiguous()) for f, n in _pieces(A, 64, [1, 2])]
+        with corr.Correlator(N, 1, C, A, "int8", stream=stream) as c:
+            def run():
+                for f, n, buf in pieces:
+                    c.fengine_real8(buf, n, inv, first_spectrum=f)
+                c.xengine(A)
+            run()
+            ref = c.dump(reset=True).cpu().numpy()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                run()
+            for rep in range(3):
+                g.replay()
+                stream.synchronize()
+                got = c.dump(reset=False).cpu().numpy()
+                assert np.array_equal(got, ref), rep
+                torch.zeros(1000, device=DEV).sum().item()
