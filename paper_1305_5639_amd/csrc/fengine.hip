@@ -1,9 +1,10 @@
 // F-engine: channelising FFT (Section 2, Eq. 1) with a fused requantise
 // epilogue that writes the X-engine's time-blocked planar spectra layout.
 //
-// One workgroup of 256 threads transforms T = 8192 / C consecutive spectra of
+// One workgroup of 256 threads transforms T = 256 PT / C consecutive spectra of
 // one input (64 KB of complex64 voltages, one contiguous coalesced run); every
-// thread holds 32 complex values.  The FFT is a Stockham autosort transform
+// thread holds PT = 32 complex values (64 for some low-precision complex forms
+// at C >= 4096).  The FFT is a Stockham autosort transform
 // with radices up to 32 done in registers: one pass for C <= 32, two for
 // C <= 1024 (one LDS round trip), three above.  The first pass reads straight
 // from global memory; the others read and write LDS rows whose index is padded
@@ -34,8 +35,20 @@ namespace corr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kTC = 8192;               // complex values per workgroup
-constexpr int kPerThread = kTC / kThreads;
+
+// Complex values per thread: 32, or 64 where 32 leaves a workgroup so few
+// spectra (8192/C) that its output rows go out in 1- to 4-byte pieces and the
+// store addressing saturates.  64 values spill a little (about 100 bytes), so
+// they are used only where they measured faster on 2^28 samples: int8 / FP8
+// from C = 4096 (1.40 -> 1.16 ms at 4096, 2.76 -> 2.09 ms at 8192) and FP16
+// at C = 8192 (2.72 -> 2.23 ms); at C = 2048 they were a third slower.  A
+// workgroup transforms T = 256 PT / C spectra; the helpers below recover PT
+// as T C / 256.
+template <int C, int PREC, bool REAL>
+constexpr int per_thread() {
+    return (!REAL && (((PREC == P_INT8 || PREC == P_FP8) && C >= 4096) || (PREC == P_FP16 && C >= 8192))) ? 64
+                                                                                                          : 32;
+}
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -132,7 +145,7 @@ __device__ __forceinline__ void bfly_index(int tid, int q, int &t, int &j) {
         t = b % T;
         j = b / T;
     } else if constexpr (MAP == MAP_PAIRED) {
-        constexpr int Q = kPerThread / R, CR = C / R, G = kThreads / T;
+        constexpr int Q = T * C / kThreads / R, CR = C / R, G = kThreads / T;
         static_assert(T <= kThreads && Q % 2 == 0 && CR == G * Q, "paired mapping needs T | 256 and even Q");
         t = tid % T;
         const int g = tid / T;
@@ -184,7 +197,7 @@ __device__ __forceinline__ char2 ld_in(const char2 *p) {
 template <int C, int T, int R, bool NT, typename Src>
 __device__ __forceinline__ void first_pass(float2 *v, const Src *__restrict__ src, int a0, int n_spectra,
                                            int tid) {
-    constexpr int Q = kPerThread / R, CR = C / R;
+    constexpr int Q = T * C / kThreads / R, CR = C / R;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int t, j;
@@ -209,7 +222,7 @@ __device__ __forceinline__ void first_pass(float2 *v, const Src *__restrict__ sr
 // W_C^(r (j mod NS) C/(NS R)) and does an R-point DFT.
 template <int C, int T, int R, int NS, int MAP>
 __device__ __forceinline__ void later_pass(float2 *v, const float2 *__restrict__ tw, int tid) {
-    constexpr int Q = kPerThread / R;
+    constexpr int Q = T * C / kThreads / R;
     constexpr int LR = ilog2(R);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -241,7 +254,8 @@ __device__ __forceinline__ void later_pass(float2 *v, const float2 *__restrict__
 // wait_first: the LDS may still be read by an earlier exchange.
 template <int C, int T, int R1, int NS1, int R2, int MAP2, bool SPLIT>
 __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wait_first) {
-    constexpr int Q1 = kPerThread / R1, Q2 = kPerThread / R2, CR2 = C / R2;
+    constexpr int PT = T * C / kThreads;
+    constexpr int Q1 = PT / R1, Q2 = PT / R2, CR2 = C / R2;
     if constexpr (!SPLIT) {
         float2 *l2 = reinterpret_cast<float2 *>(lds);
         if (wait_first) __syncthreads();
@@ -263,7 +277,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
         }
         return;
     }
-    float xr[kPerThread];
+    float xr[PT];
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
         if (comp == 1 || wait_first) __syncthreads();
@@ -294,10 +308,10 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 // and how the real-input form finds the partner Z[C - k] of each Z[k]: in the
 // same thread (MAP_PAIRED, or C/R = 1 where every butterfly has j = 0), else
 // through LDS.
-template <int C> struct Last {
+template <int C, int PT = 32> struct Last {
     using P = Plan<C>;
     static constexpr int RL = P::NP == 1 ? P::R0 : (P::NP == 2 ? P::R1 : P::R2);
-    static constexpr int Q = kPerThread / RL, CR = C / RL;
+    static constexpr int Q = PT / RL, CR = C / RL;
     static constexpr bool PAIRED = CR >= 2 && Q % 2 == 0;
     static constexpr bool REAL_VIA_LDS = CR >= 2 && Q % 2 == 1;
 };
@@ -353,7 +367,7 @@ __device__ __forceinline__ void split_j0(float2 *u, const float2 *__restrict__ t
 // paired with itself (r with RL - r, and r with RL-1-r).
 template <int C, int T, int RL>
 __device__ __forceinline__ void real_split_regs(float2 *v, const float2 *__restrict__ tw2, int tid) {
-    constexpr int Q = kPerThread / RL, CR = C / RL;
+    constexpr int Q = T * C / kThreads / RL, CR = C / RL;
     if constexpr (CR == 1) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) split_j0<C, RL>(v + q * RL, tw2);
@@ -387,8 +401,9 @@ __device__ __forceinline__ void real_split_regs(float2 *v, const float2 *__restr
 // SPLIT.  The LDS may still be read by the last reordering on entry.
 template <int C, int T, int RL, bool SPLIT>
 __device__ __forceinline__ void real_split_lds(float2 *v, float *lds, const float2 *__restrict__ tw2, int tid) {
-    constexpr int Q = kPerThread / RL, CR = C / RL;
-    float pr[kPerThread];                              // partner real parts (SPLIT)
+    constexpr int PT = T * C / kThreads;
+    constexpr int Q = PT / RL, CR = C / RL;
+    float pr[PT];                                      // partner real parts (SPLIT)
 #pragma unroll
     for (int comp = 0; comp < (SPLIT ? 2 : 1); ++comp) {
         __syncthreads();
@@ -473,13 +488,14 @@ template <> struct Bytes<16> { using T = uint4; };
 // never null (the host passes a table of ones for "no scale").
 template <int C, int PREC, bool REAL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
-    PREC == P_FP32 || (REAL && Last<C>::REAL_VIA_LDS) ? 2 : 3))) void fengine_kernel(
+    PREC == P_FP32 || (REAL && Last<C>::REAL_VIA_LDS) || per_thread<C, PREC, REAL>() == 64 ? 2 : 3))) void fengine_kernel(
     const void *__restrict__ in, int64_t ld, int N, int n_spectra, int n_valid_pad,
     int n_work, const float *__restrict__ inv_scale,
     const float2 *__restrict__ tw, const float2 *__restrict__ tw2, uint8_t *__restrict__ spec, int n_tb_cap,
     int tb0) {
     using E = typename Elem<PREC>::T;
-    constexpr int T = kTC / C;                         // spectra per workgroup
+    constexpr int PT = per_thread<C, PREC, REAL>();   // complex values per thread
+    constexpr int T = kThreads * PT / C;               // spectra per workgroup
     using P = Plan<C>;
     static_assert(P::R0 * P::R1 * P::R2 == C, "radix plan must multiply to C");
     constexpr int RL = Last<C>::RL;                    // last radix
@@ -531,7 +547,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const int p = rest % N;
     const int a0 = ((rest / N) * GPT + w % GPT) * T;
 
-    float2 v[kPerThread];
+    float2 v[PT];
     if constexpr (REAL) {
         const char2 *src = reinterpret_cast<const char2 *>(static_cast<const int8_t *>(in) + (int64_t)p * ld);
         fft<C, T, SPLIT, LMAP, false>(v, lds, src, a0, n_spectra, tw, tid);
@@ -557,7 +573,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     for (int pl0 = 0; pl0 < 2; pl0 += NPL) {
         __syncthreads();                               // every thread is done reading lds
 #pragma unroll
-        for (int q = 0; q < kPerThread / RL; ++q) {
+        for (int q = 0; q < PT / RL; ++q) {
             int t, j;
             bfly_index<C, T, RL, LMAP>(tid, q, t, j);
 #pragma unroll
@@ -588,7 +604,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 template <int PREC, int C, bool REAL>
 hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
                     const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, int tb0, hipStream_t stream) {
-    constexpr int T = kTC / C;
+    constexpr int T = kThreads * per_thread<C, PREC, REAL>() / C;
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
     const int n_valid_pad = n_tb * TB;

@@ -44,7 +44,8 @@ def test_fengine_fp32_matches_dft(N, C, A, ldpad):
 
 
 @pytest.mark.parametrize("prec", ["int8", "fp16", "fp8"])
-@pytest.mark.parametrize("N,C,A", [(6, 64, 70), (3, 1024, 5), (2, 16, 200), (2, 8192, 3), (3, 2048, 9)])
+@pytest.mark.parametrize("N,C,A", [(6, 64, 70), (3, 1024, 5), (2, 16, 200), (2, 8192, 3), (3, 2048, 9),
+                                   (2, 4096, 4)])
 def test_fengine_requantiser_parity(prec, N, C, A):
     """Requantised spectra equal the oracle's rounding of the float64 DFT,
     except at rounding ties closer than the FP32 FFT error."""
