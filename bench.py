@@ -2,8 +2,9 @@
 
 One step = one pass of the whole hot path over one integration of synthetic
 voltages already resident in HBM: F-engine (channelising FFT + requantise),
-X-engine (Eq. 2 over the triangle of all input pairs, autos included), and a
-dump of the visibilities to a device buffer with reset.
+X-engine (Eq. 2 over the triangle of all input pairs, autos included), and the
+dump of the visibilities to a device buffer with reset, fused into the
+X-engine's epilogue (corr_xengine_dump).
 
 Default workload: 128 stations x 2 pols (256 inputs), 1024 channels, 1000
 spectra per integration, FP32 (complex64 Gaussian voltages plus three
@@ -25,6 +26,8 @@ Also reported on one JSON line:
                   type's MFMA peak;
   batched      -- 64 uneven sub-arrays: persistent batched X-engine vs
                   per-array launches, and the graph-replayed step;
+  paper_workload -- 8-bit real samples, transform length 256, 128 to 3072
+                  streams (the paper's own tests), FP32 and int8;
   cpu_baseline -- the oracle (float64 direct DFT + triple-loop correlation)
                   timed on a bounded channel sample on the host cores, which
                   also gives each form's error against float64.
@@ -140,12 +143,14 @@ class Timer:
 
 
 def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
-    """Time steps of F + X + dump; X timed on its own with events."""
+    """Time steps of F + X + dump, the dump fused into the X-engine
+    (corr_xengine_dump writes the integration to the output buffer and
+    resets); F and X timed on their own with events."""
     inv = torch.from_numpy(synth.inv_scale(w, prec)).to("cuda") if prec != "fp32" else None
     c = corr.Correlator(w.n_stations, w.n_pols, w.n_channels, w.n_integrate, prec)
     out = c.new_visibilities()
     A = w.n_integrate
-    ftimer, xtimer, dtimer = Timer(torch), Timer(torch), Timer(torch)
+    ftimer, xtimer = Timer(torch), Timer(torch)
 
     def step(timed):
         if timed:
@@ -154,13 +159,9 @@ def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
         if timed:
             ftimer.stop(s)
             s = xtimer.start()
-        c.xengine(A)
+        c.xengine_dump(A, out)
         if timed:
             xtimer.stop(s)
-            s = dtimer.start()
-        c.dump(out, reset=True)
-        if timed:
-            dtimer.stop(s)
 
     for _ in range(warmup):
         step(False)
@@ -170,7 +171,7 @@ def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
         step(True)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    timing = {"fengine_ms": ftimer.stats(), "xengine_ms": xtimer.stats(), "dump_ms": dtimer.stats()}
+    timing = {"fengine_ms": ftimer.stats(), "xengine_and_dump_ms": xtimer.stats()}
     return c, out, inv, wall, ftimer.mean_ms(), xtimer.mean_ms(), timing
 
 
@@ -600,7 +601,7 @@ def main():
         "config": {"workload": w.name, "n_stations": w.n_stations, "n_pols": w.n_pols,
                    "n_inputs": N, "n_channels": C, "n_integrate": A, "precision": prec,
                    "products": B, "cmac_per_step": cmacs,
-                   "step": "F-engine + X-engine + dump to device (reset)"},
+                   "step": "F-engine + X-engine with the dump to a device buffer (reset) fused into its epilogue"},
         "xengine_ms": x_ms,
         "fengine_ms": f_ms,
         "xengine_tcmacs": cmacs / (x_ms * 1e-3) / 1e12,

@@ -209,6 +209,22 @@ CORR_API corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t 
                          const float *d_inv_scale);
 
 /*
+ * The last X-engine call of an integration fused with its dump: as
+ * corr_xengine, but the integrated visibilities (the accumulators' sums plus
+ * this call's) are written straight to d_dst, in the dump's lower-triangle,
+ * channel-major layout and units, instead of back into the accumulators, and
+ * the integration is reset -- the same result as corr_xengine followed by
+ * corr_dump_visibilities(h, d_dst, 1, 1), without the copy.
+ *   d_dst : device pointer, 8-byte aligned, corr_visibility_bytes(params)
+ *           bytes.
+ * Handles whose layout is not CORR_TRI_LOWER / CORR_CHAN_MAJOR are
+ * CORR_E_UNSUPPORTED; batch sub-array handles are CORR_E_STATE.  The other
+ * arguments and errors are as for corr_xengine.
+ */
+CORR_API corr_status corr_xengine_dump(corr_handle h, const void *d_spectra, int32_t n_spectra,
+                                       const float *d_inv_scale, void *d_dst);
+
+/*
  * Write the integrated visibilities to dst in the handle's layout and order:
  * complex64 per product for the float forms (scaled to voltage units),
  * (re, im) int32 per product for CORR_INT8 (raw integer sums, exact).

@@ -44,7 +44,7 @@ ABI_FUNCTIONS = (
     "corr_copy_spectra", "corr_get_counts", "corr_status_string", "corr_last_error",
     "corr_set_tile", "corr_autotune", "corr_create_batched", "corr_batch_get",
     "corr_xengine_batched", "corr_destroy_batched", "corr_xengine_rect", "corr_fengine_real8",
-    "corr_fengine_at", "corr_fengine_real8_at",
+    "corr_fengine_at", "corr_fengine_real8_at", "corr_xengine_dump",
 )
 
 
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.corr_fengine_at.argtypes = [P, P, i64, i32, P, i32]
         L.corr_fengine_real8_at.argtypes = [P, P, i64, i32, P, i32]
         L.corr_xengine.argtypes = [P, P, i32, P]
+        L.corr_xengine_dump.argtypes = [P, P, i32, P, P]
         L.corr_dump_visibilities.argtypes = [P, P, i32, i32]
         L.corr_copy_spectra.argtypes = [P, P, i32]
         L.corr_get_counts.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64)]
@@ -109,7 +110,7 @@ def lib() -> ctypes.CDLL:
         L.corr_destroy_batched.argtypes = [P]
         L.corr_xengine_rect.argtypes = [P, i32, i32, i32, i32, i32, P, i32]
         for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_fengine_real8", "corr_fengine_at",
-                  "corr_fengine_real8_at", "corr_xengine",
+                  "corr_fengine_real8_at", "corr_xengine", "corr_xengine_dump",
                   "corr_xengine_rect",
                   "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts", "corr_set_tile",
                   "corr_autotune", "corr_create_batched", "corr_batch_get", "corr_xengine_batched",
@@ -228,6 +229,11 @@ def corr_xengine(h, spectra, n_spectra: int, inv_scale=None) -> None:
     _check(lib().corr_xengine(h, _ptr(spectra), int(n_spectra), _ptr(inv_scale)), "corr_xengine", h)
 
 
+def corr_xengine_dump(h, spectra, n_spectra: int, inv_scale, dst) -> None:
+    _check(lib().corr_xengine_dump(h, _ptr(spectra), int(n_spectra), _ptr(inv_scale), _ptr(dst)),
+           "corr_xengine_dump", h)
+
+
 def corr_xengine_rect(h, i0: int, ni: int, j0: int, nj: int, n_spectra: int, out, accumulate: bool = False) -> None:
     _check(lib().corr_xengine_rect(h, int(i0), int(ni), int(j0), int(nj), int(n_spectra), _ptr(out),
                                    int(bool(accumulate))), "corr_xengine_rect", h)
@@ -308,6 +314,14 @@ class Correlator:
 
     def xengine(self, n_spectra, spectra=None, inv_scale=None):
         corr_xengine(self.handle, spectra, n_spectra, inv_scale)
+
+    def xengine_dump(self, n_spectra, dst=None, spectra=None, inv_scale=None):
+        """Last X-engine call of an integration, its result written straight to
+        dst (a device tensor from new_visibilities()); the integration resets."""
+        if dst is None:
+            dst = self.new_visibilities()
+        corr_xengine_dump(self.handle, spectra, n_spectra, inv_scale, dst)
+        return dst
 
     def xengine_rect(self, i0, ni, j0, nj, n_spectra, out=None, accumulate=False):
         """Rows [i0, i0+ni) against columns [j0, j0+nj) of the held spectra:

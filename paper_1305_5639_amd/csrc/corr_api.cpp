@@ -423,8 +423,12 @@ corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, int64_t l
     return corr_fengine_real8_at(h, d_samples, ld_samples, n_spectra, d_inv_scale, 0);
 }
 
-corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra, const float *d_inv_scale) {
-    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+}  // extern "C"
+
+// Checks of an X-engine call, the ingest of caller spectra, and the scale the
+// X-engine applies (shared by corr_xengine and corr_xengine_dump).
+static corr_status prepare_x(corr_ctx *h, const void *d_spectra, int32_t n_spectra, const float *d_inv_scale,
+                             const float **s2_out) {
     if (n_spectra < 1) return fail(h, CORR_E_INVALID_ARG, "n_spectra must be >= 1");
     if (d_spectra) {
         if (!aligned(d_spectra, 16)) return fail(h, CORR_E_INVALID_ARG, "d_spectra must be 16-byte aligned");
@@ -455,11 +459,41 @@ corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra
     } else {
         s2 = x_scale(h);
     }
-    e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->n_tb_cap, h->spec, s2, h->acc,
-                       h->acc_zero ? 1 : 0, h->stream);
+    *s2_out = s2;
+    return CORR_OK;
+}
+
+extern "C" {
+
+corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra, const float *d_inv_scale) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    const float *s2 = nullptr;
+    const corr_status st = prepare_x(h, d_spectra, n_spectra, d_inv_scale, &s2);
+    if (st != CORR_OK) return st;
+    const hipError_t e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->n_tb_cap, h->spec,
+                                        s2, h->acc, h->acc, h->acc_zero ? 1 : 0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
     h->acc_zero = false;
     h->n_integrated += n_spectra;
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_xengine_dump(corr_handle h, const void *d_spectra, int32_t n_spectra, const float *d_inv_scale,
+                              void *d_dst) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (!d_dst || !aligned(d_dst, 8)) return fail(h, CORR_E_INVALID_ARG, "d_dst must be an 8-byte aligned device pointer");
+    if (!default_dump(&h->p))
+        return fail(h, CORR_E_UNSUPPORTED, "the fused dump writes the lower-triangle, channel-major layout only");
+    if (h->batch_member) return fail(h, CORR_E_STATE, "sub-array handles integrate with corr_xengine_batched");
+    const float *s2 = nullptr;
+    const corr_status st = prepare_x(h, d_spectra, n_spectra, d_inv_scale, &s2);
+    if (st != CORR_OK) return st;
+    const hipError_t e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->n_tb_cap, h->spec,
+                                        s2, d_dst, h->acc, h->acc_zero ? 1 : 0, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
+    h->acc_zero = true;                                  // the integration ends here: reset
+    h->n_integrated = 0;
     h->err.clear();
     return CORR_OK;
 }
@@ -607,10 +641,11 @@ corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile_out) {
     int best = 0;
     for (int c : cand) {
         float ms = 0;
-        e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->n_tb_cap, h->spec, x_scale(h), tmp, 1, h->stream);
+        e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->n_tb_cap, h->spec, x_scale(h), tmp, tmp, 1,
+                           h->stream);
         for (int r = 0; e == hipSuccess && r < 3; ++r) {
             (void)hipEventRecord(ev[0], h->stream);
-            e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->n_tb_cap, h->spec, x_scale(h), tmp, 1,
+            e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->n_tb_cap, h->spec, x_scale(h), tmp, tmp, 1,
                                h->stream);
             (void)hipEventRecord(ev[1], h->stream);
             if (e == hipSuccess) e = hipEventSynchronize(ev[1]);

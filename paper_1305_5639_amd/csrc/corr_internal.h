@@ -65,9 +65,12 @@ hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, i
 // buffer into acc (spectra past n_spectra in the last time block are masked to
 // zero), with square blocks of `tile` (64 or 128) inputs.  scale2 (float
 // forms, may be null = 1): per-channel s_k^2 applied to the integrated
-// products.  first_call = 1 writes instead of read-modify-write.
+// products.  first_call = 1 writes instead of read-modify-write.  The sums so
+// far are read from acc_in (acc itself, or the accumulators when acc is a
+// dump destination in the accumulator layout).
 hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
-                          const float *scale2, void *acc, int first_call, hipStream_t stream);
+                          const float *scale2, void *acc, const void *acc_in, int first_call,
+                          hipStream_t stream);
 
 // Rectangle X-engine: rows [r0, r0 + ni) against columns [c0, c0 + nj) of the
 // held spectra (disjoint ranges), into out [C][ni][nj] (re, im) pairs, written

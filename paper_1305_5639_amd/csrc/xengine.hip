@@ -243,7 +243,8 @@ struct OutMap {
 template <int PREC, int TILE, bool RECT = false>
 __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ base_k, int N, int n_tb, int tv,
                                      int I0, int J0, int k, const float *__restrict__ scale2,
-                                     void *__restrict__ acc_out, int64_t B, int first_call, int tid,
+                                     void *__restrict__ acc_out, const void *acc_in, int64_t B, int first_call,
+                                     int tid,
                                      OutMap om = OutMap{}) {
     constexpr int NT = kNT, RB = kRB, CPP = kCPP;
     using Acc = typename XT<PREC, NT>::Acc;
@@ -354,6 +355,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     typedef E T2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(1))) T2 gT2;
     gT2 *out = (gT2 *)acc_out + (int64_t)k * B;
+    const gT2 *in = (const gT2 *)acc_in + (int64_t)k * B;   // the sums so far (== out except when dumping)
     const float s2 = (PREC != P_INT8 && scale2) ? ((gf32 *)scale2)[k] : 1.0f;
     const int j = J0 + wj * 32 + m;
     // rows of a block per batch of accumulator reads: all 16 where a wave has
@@ -385,7 +387,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
             T2 old[EH];
             if (!first_call) {
 #pragma unroll
-                for (int q = 0; q < EH; ++q) old[q] = out[idx[q]];
+                for (int q = 0; q < EH; ++q) old[q] = in[idx[q]];
             }
 #pragma unroll
             for (int q = 0; q < EH; ++q) {
@@ -421,7 +423,7 @@ __device__ __forceinline__ void tri_block(int t, int &bi, int &bj) {
 template <int PREC, int TILE>
 __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(4))) void xengine_kernel(
     const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
-    int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, int64_t B,
+    int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, const void *acc_in, int64_t B,
     int first_call) {
     __shared__ __attribute__((aligned(16))) uint8_t smem[ring_bytes(TILE)];
     const int per = (n_work + 7) / 8;
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
     int bi, bj;
     tri_block(w % n_tiles, bi, bj);
     tile<PREC, TILE>(smem, spec + (int64_t)k * k_stride, N, n_tb, tv, bi * TILE, bj * TILE, k, scale2, acc_out,
-                     B, first_call, threadIdx.x);
+                     acc_in, B, first_call, threadIdx.x);
 }
 
 // Rectangle X-engine: rows [r0, r0 + ni) against columns [c0, c0 + nj) in
@@ -447,7 +449,7 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
     const int nb = nbi * nbj;
     const int k = w / nb, bi = (w % nb) / nbj, bj = w % nbj;
     tile<PREC, TILE, true>(smem, spec + (int64_t)k * k_stride, N, n_tb, tv, om.r0 + bi * TILE, om.c0 + bj * TILE, k,
-                           scale2, out, B, first_call, threadIdx.x, om);
+                           scale2, out, out, B, first_call, threadIdx.x, om);
 }
 
 // Persistent X-engine over many sub-arrays with blocks of TILE inputs, so
@@ -499,7 +501,7 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
             int t = tid;
             asm volatile("" : "+v"(t));
             tile<PREC, TILE>(smem, d.spec + (int64_t)k * d.k_stride, d.N, d.n_tb, d.tv, bi * TILE, bj * TILE, k,
-                             d.scale2, d.acc, d.B, d.first_call, t);
+                             d.scale2, d.acc, d.acc, d.B, d.first_call, t);
             if (tid == 0) s_item = next;
             __syncthreads();                            // also: every wave is done with smem
             item = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_item);
@@ -512,7 +514,7 @@ __global__ void reset_counters_kernel(unsigned int *counter) { counter[threadIdx
 
 template <int PREC, int TILE>
 hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
-                    void *acc, int first_call, hipStream_t stream) {
+                    void *acc, const void *acc_in, int first_call, hipStream_t stream) {
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
     const int tv = n_spectra - (n_tb - 1) * TB;
@@ -525,15 +527,16 @@ hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec,
     const int64_t B = (int64_t)N * (N + 1) / 2;
     hipLaunchKernelGGL((xengine_kernel<PREC, TILE>), dim3(grid), dim3(WaveGrid<TILE>::THREADS), 0, stream,
                        static_cast<const uint8_t *>(spec), N, n_tiles, (int)n_work, n_tb, tv, k_stride,
-                       scale2, acc, B, first_call);
+                       scale2, acc, acc_in, B, first_call);
     return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t launch_xp(int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
-                     void *acc, int first_call, hipStream_t stream) {
-    if (tile == 64) return launch_x<PREC, 64>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
-    if (tile == 128) return launch_x<PREC, 128>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+                     void *acc, const void *acc_in, int first_call, hipStream_t stream) {
+    if (tile == 64) return launch_x<PREC, 64>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
+    if (tile == 128)
+        return launch_x<PREC, 128>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
     return hipErrorInvalidValue;
 }
 
@@ -581,12 +584,12 @@ hipError_t launch_xengine_rect(int prec, int tile, int C, int N, int n_spectra, 
 }
 
 hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
-                          const float *scale2, void *acc, int first_call, hipStream_t stream) {
+                          const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream) {
     switch (prec) {
-    case P_FP32: return launch_xp<P_FP32>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
-    case P_FP16: return launch_xp<P_FP16>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
-    case P_FP8: return launch_xp<P_FP8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
-    case P_INT8: return launch_xp<P_INT8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, first_call, stream);
+    case P_FP32: return launch_xp<P_FP32>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
+    case P_FP16: return launch_xp<P_FP16>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
+    case P_FP8: return launch_xp<P_FP8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
+    case P_INT8: return launch_xp<P_INT8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
     default: return hipErrorInvalidValue;
     }
 }
