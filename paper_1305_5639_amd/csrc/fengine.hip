@@ -1,7 +1,8 @@
 // F-engine: channelising FFT (Section 2, Eq. 1) with a fused requantise
 // epilogue that writes the X-engine's time-blocked planar spectra layout.
 //
-// One workgroup of 256 threads transforms T = 256 PT / C consecutive spectra of
+// One workgroup of TH threads (256, or 512 for some int8 / FP8 sizes)
+// transforms T = TH PT / C consecutive spectra of
 // one input (64 KB of complex64 voltages, one contiguous coalesced run); every
 // thread holds PT = 32 complex values (64 for some low-precision complex forms
 // at C >= 4096).  The FFT is a Stockham autosort transform
@@ -34,7 +35,14 @@
 namespace corr {
 namespace {
 
-constexpr int kThreads = 256;
+// Threads per workgroup: 256, or 512 for the int8 / FP8 complex forms at C =
+// 512, 1024 and 8192, where twice the spectra per workgroup (so half as many
+// partial output rows) measured 3-17% faster on 2^28 samples; at 256, 2048 and
+// 4096 channels they gained nothing or lost (4096: 34% slower).
+template <int C, int PREC, bool REAL>
+constexpr int threads() {
+    return (!REAL && (PREC == P_INT8 || PREC == P_FP8) && (C == 512 || C == 1024 || C == 8192)) ? 512 : 256;
+}
 
 // Complex values per thread: 32, or 64 where 32 leaves a workgroup so few
 // spectra (8192/C) that its output rows go out in 1- to 4-byte pieces and the
@@ -42,8 +50,8 @@ constexpr int kThreads = 256;
 // they are used only where they measured faster on 2^28 samples: int8 / FP8
 // from C = 4096 (1.40 -> 1.16 ms at 4096, 2.76 -> 2.09 ms at 8192) and FP16
 // at C = 8192 (2.72 -> 2.23 ms); at C = 2048 they were a third slower.  A
-// workgroup transforms T = 256 PT / C spectra; the helpers below recover PT
-// as T C / 256.
+// workgroup of TH threads transforms T = TH PT / C spectra; the helpers below
+// recover PT as T C / TH.
 template <int C, int PREC, bool REAL>
 constexpr int per_thread() {
     return (!REAL && (((PREC == P_INT8 || PREC == P_FP8) && C >= 4096) || (PREC == P_FP16 && C >= 8192))) ? 64
@@ -126,27 +134,27 @@ template <> struct Plan<8192> { static constexpr int NP = 3, R0 = 8, R1 = 32, R2
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 // Butterfly q of thread tid in a pass of radix R maps to (spectrum t, index
-// j), with b = tid + 256 q:
+// j), with b = tid + TH q (TH threads per workgroup):
 //   MAP_PLAIN : (b / (C/R), b % (C/R));
 //   MAP_REMAP : (b % T, b / T), the last pass, so that neighbouring lanes hold
 //               neighbouring spectra of one channel;
 //   MAP_PAIRED: the last pass of the real-input form when C/R >= 2 and the Q
 //               butterflies of a thread are even in number: t = tid % T, and
-//               with g = tid / T, G = 256 / T, butterfly q < Q/2 takes
+//               with g = tid / T, G = TH / T, butterfly q < Q/2 takes
 //               j = g + G q while butterfly Q-1-q takes its mirror C/R - j (C/R/2
 //               in place of the mirror of j = 0), so a thread holds channel k
 //               and channel C - k of the same spectrum together.
 enum { MAP_PLAIN = 0, MAP_REMAP = 1, MAP_PAIRED = 2 };
 
-template <int C, int T, int R, int MAP>
+template <int C, int T, int TH, int R, int MAP>
 __device__ __forceinline__ void bfly_index(int tid, int q, int &t, int &j) {
-    const int b = tid + kThreads * q;
+    const int b = tid + TH * q;
     if constexpr (MAP == MAP_REMAP) {
         t = b % T;
         j = b / T;
     } else if constexpr (MAP == MAP_PAIRED) {
-        constexpr int Q = T * C / kThreads / R, CR = C / R, G = kThreads / T;
-        static_assert(T <= kThreads && Q % 2 == 0 && CR == G * Q, "paired mapping needs T | 256 and even Q");
+        constexpr int Q = T * C / TH / R, CR = C / R, G = TH / T;
+        static_assert(T <= TH && Q % 2 == 0 && CR == G * Q, "paired mapping needs T | TH and even Q");
         t = tid % T;
         const int g = tid / T;
         if (q < Q / 2) {
@@ -194,14 +202,14 @@ __device__ __forceinline__ char2 ld_in(const char2 *p) {
     return *p;
 }
 
-template <int C, int T, int R, bool NT, typename Src>
+template <int C, int T, int TH, int R, bool NT, typename Src>
 __device__ __forceinline__ void first_pass(float2 *v, const Src *__restrict__ src, int a0, int n_spectra,
                                            int tid) {
-    constexpr int Q = T * C / kThreads / R, CR = C / R;
+    constexpr int Q = T * C / TH / R, CR = C / R;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int t, j;
-        bfly_index<C, T, R, MAP_PLAIN>(tid, q, t, j);
+        bfly_index<C, T, TH, R, MAP_PLAIN>(tid, q, t, j);
         float2 *x = v + q * R;
         const bool ok = (a0 + t) < n_spectra;
         const Src *row = src + (int64_t)(ok ? a0 + t : 0) * C + j;
@@ -220,14 +228,14 @@ __device__ __forceinline__ void first_pass(float2 *v, const Src *__restrict__ sr
 // A later pass of radix R after NS points have been combined: butterfly (t, j)
 // (already holding x[t][j + r C/R]) multiplies element r by
 // W_C^(r (j mod NS) C/(NS R)) and does an R-point DFT.
-template <int C, int T, int R, int NS, int MAP>
+template <int C, int T, int TH, int R, int NS, int MAP>
 __device__ __forceinline__ void later_pass(float2 *v, const float2 *__restrict__ tw, int tid) {
-    constexpr int Q = T * C / kThreads / R;
+    constexpr int Q = T * C / TH / R;
     constexpr int LR = ilog2(R);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int t, j;
-        bfly_index<C, T, R, MAP>(tid, q, t, j);
+        bfly_index<C, T, TH, R, MAP>(tid, q, t, j);
         float2 *x = v + q * R;
         const int m = (j % NS) * (C / (NS * R));
         float2 wp[LR];                                 // W^(m 2^i)
@@ -252,9 +260,9 @@ __device__ __forceinline__ void later_pass(float2 *v, const float2 *__restrict__
 // back taking the registers of one just written (half the LDS, so more
 // workgroups per CU); otherwise whole complex values in one round.
 // wait_first: the LDS may still be read by an earlier exchange.
-template <int C, int T, int R1, int NS1, int R2, int MAP2, bool SPLIT>
+template <int C, int T, int TH, int R1, int NS1, int R2, int MAP2, bool SPLIT>
 __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wait_first) {
-    constexpr int PT = T * C / kThreads;
+    constexpr int PT = T * C / TH;
     constexpr int Q1 = PT / R1, Q2 = PT / R2, CR2 = C / R2;
     if constexpr (!SPLIT) {
         float2 *l2 = reinterpret_cast<float2 *>(lds);
@@ -262,7 +270,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 #pragma unroll
         for (int q = 0; q < Q1; ++q) {
             int t, j;
-            bfly_index<C, T, R1, MAP_PLAIN>(tid, q, t, j);
+            bfly_index<C, T, TH, R1, MAP_PLAIN>(tid, q, t, j);
             const int base = (j / NS1) * NS1 * R1 + (j % NS1);
 #pragma unroll
             for (int r = 0; r < R1; ++r) l2[lidx<C>(t, base + r * NS1)] = v[q * R1 + r];
@@ -271,7 +279,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 #pragma unroll
         for (int q = 0; q < Q2; ++q) {
             int t, j;
-            bfly_index<C, T, R2, MAP2>(tid, q, t, j);
+            bfly_index<C, T, TH, R2, MAP2>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < R2; ++r) v[q * R2 + r] = l2[lidx<C>(t, j + r * CR2)];
         }
@@ -284,7 +292,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 #pragma unroll
         for (int q = 0; q < Q1; ++q) {
             int t, j;
-            bfly_index<C, T, R1, MAP_PLAIN>(tid, q, t, j);
+            bfly_index<C, T, TH, R1, MAP_PLAIN>(tid, q, t, j);
             const int base = (j / NS1) * NS1 * R1 + (j % NS1);
 #pragma unroll
             for (int r = 0; r < R1; ++r) lds[lidx<C>(t, base + r * NS1)] = comp ? v[q * R1 + r].y : v[q * R1 + r].x;
@@ -293,7 +301,7 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int tid, bool wa
 #pragma unroll
         for (int q = 0; q < Q2; ++q) {
             int t, j;
-            bfly_index<C, T, R2, MAP2>(tid, q, t, j);
+            bfly_index<C, T, TH, R2, MAP2>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < R2; ++r) {
                 const float e = lds[lidx<C>(t, j + r * CR2)];
@@ -318,19 +326,19 @@ template <int C, int PT = 32> struct Last {
 
 // The passes of Plan<C>; v ends with the last pass's outputs in registers,
 // laid out by mapping LMAP.
-template <int C, int T, bool SPLIT, int LMAP, bool NT, typename Src>
+template <int C, int T, int TH, bool SPLIT, int LMAP, bool NT, typename Src>
 __device__ __forceinline__ void fft(float2 *v, float *lds, const Src *__restrict__ src, int a0, int n_spectra,
                                     const float2 *__restrict__ tw, int tid) {
     using P = Plan<C>;
-    first_pass<C, T, P::R0, NT>(v, src, a0, n_spectra, tid);
+    first_pass<C, T, TH, P::R0, NT>(v, src, a0, n_spectra, tid);
     if constexpr (P::NP == 2) {
-        exchange<C, T, P::R0, 1, P::R1, LMAP, SPLIT>(v, lds, tid, false);
-        later_pass<C, T, P::R1, P::R0, LMAP>(v, tw, tid);
+        exchange<C, T, TH, P::R0, 1, P::R1, LMAP, SPLIT>(v, lds, tid, false);
+        later_pass<C, T, TH, P::R1, P::R0, LMAP>(v, tw, tid);
     } else if constexpr (P::NP == 3) {
-        exchange<C, T, P::R0, 1, P::R1, MAP_PLAIN, SPLIT>(v, lds, tid, false);
-        later_pass<C, T, P::R1, P::R0, MAP_PLAIN>(v, tw, tid);
-        exchange<C, T, P::R1, P::R0, P::R2, LMAP, SPLIT>(v, lds, tid, true);
-        later_pass<C, T, P::R2, P::R0 * P::R1, LMAP>(v, tw, tid);
+        exchange<C, T, TH, P::R0, 1, P::R1, MAP_PLAIN, SPLIT>(v, lds, tid, false);
+        later_pass<C, T, TH, P::R1, P::R0, MAP_PLAIN>(v, tw, tid);
+        exchange<C, T, TH, P::R1, P::R0, P::R2, LMAP, SPLIT>(v, lds, tid, true);
+        later_pass<C, T, TH, P::R2, P::R0 * P::R1, LMAP>(v, tw, tid);
     }
 }
 
@@ -365,14 +373,14 @@ __device__ __forceinline__ void split_j0(float2 *u, const float2 *__restrict__ t
 // element RL-1-r of butterfly Q-1-q (index C/R - j); the thread with g = 0
 // instead holds j = 0 in butterfly 0 and j = C/R/2 in butterfly Q-1, each
 // paired with itself (r with RL - r, and r with RL-1-r).
-template <int C, int T, int RL>
+template <int C, int T, int TH, int RL>
 __device__ __forceinline__ void real_split_regs(float2 *v, const float2 *__restrict__ tw2, int tid) {
-    constexpr int Q = T * C / kThreads / RL, CR = C / RL;
+    constexpr int Q = T * C / TH / RL, CR = C / RL;
     if constexpr (CR == 1) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) split_j0<C, RL>(v + q * RL, tw2);
     } else {
-        constexpr int G = kThreads / T;
+        constexpr int G = TH / T;
         const int g = tid / T;
 #pragma unroll
         for (int q = 0; q < Q / 2; ++q) {
@@ -395,13 +403,13 @@ __device__ __forceinline__ void real_split_regs(float2 *v, const float2 *__restr
 // with P = Z[(C - k) mod C] of the C-point transform Z of z[n] = x[2n] + j x[2n+1],
 //   E = (Z[k] + conj P) / 2,  O = (Z[k] - conj P) / 2j,  X[k] = E + W_2C^k O,
 // k < C, W_2C^k = exp(-j pi k / C) = tw2[k].  v holds Z[k] as the last pass
-// left it (k = j + r C/RL of spectrum t, butterfly b = tid + 256 q, (t, j) =
+// left it (k = j + r C/RL of spectrum t, butterfly b = tid + TH q, (t, j) =
 // (b % T, b / T)) and receives X[k] in the same places.  The partner values
 // travel through LDS in natural [t][k] order, one component at a time when
 // SPLIT.  The LDS may still be read by the last reordering on entry.
-template <int C, int T, int RL, bool SPLIT>
+template <int C, int T, int TH, int RL, bool SPLIT>
 __device__ __forceinline__ void real_split_lds(float2 *v, float *lds, const float2 *__restrict__ tw2, int tid) {
-    constexpr int PT = T * C / kThreads;
+    constexpr int PT = T * C / TH;
     constexpr int Q = PT / RL, CR = C / RL;
     float pr[PT];                                      // partner real parts (SPLIT)
 #pragma unroll
@@ -410,7 +418,7 @@ __device__ __forceinline__ void real_split_lds(float2 *v, float *lds, const floa
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             int t, j;
-            bfly_index<C, T, RL, MAP_REMAP>(tid, q, t, j);
+            bfly_index<C, T, TH, RL, MAP_REMAP>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int i = lidx<C>(t, j + r * CR);
@@ -422,7 +430,7 @@ __device__ __forceinline__ void real_split_lds(float2 *v, float *lds, const floa
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             int t, j;
-            bfly_index<C, T, RL, MAP_REMAP>(tid, q, t, j);
+            bfly_index<C, T, TH, RL, MAP_REMAP>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int k = j + r * CR;
@@ -487,15 +495,16 @@ template <> struct Bytes<16> { using T = uint4; };
 // complex samples, block a at sample a*C) and tw2 is unused.  inv_scale is
 // never null (the host passes a table of ones for "no scale").
 template <int C, int PREC, bool REAL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+__global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_waves_per_eu(
     PREC == P_FP32 || (REAL && Last<C>::REAL_VIA_LDS) || per_thread<C, PREC, REAL>() == 64 ? 2 : 3))) void fengine_kernel(
     const void *__restrict__ in, int64_t ld, int N, int n_spectra, int n_valid_pad,
     int n_work, const float *__restrict__ inv_scale,
     const float2 *__restrict__ tw, const float2 *__restrict__ tw2, uint8_t *__restrict__ spec, int n_tb_cap,
     int tb0) {
     using E = typename Elem<PREC>::T;
+    constexpr int TH = threads<C, PREC, REAL>();      // threads per workgroup
     constexpr int PT = per_thread<C, PREC, REAL>();   // complex values per thread
-    constexpr int T = kThreads * PT / C;               // spectra per workgroup
+    constexpr int T = TH * PT / C;                     // spectra per workgroup
     using P = Plan<C>;
     static_assert(P::R0 * P::R1 * P::R2 == C, "radix plan must multiply to C");
     constexpr int RL = Last<C>::RL;                    // last radix
@@ -550,11 +559,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     float2 v[PT];
     if constexpr (REAL) {
         const char2 *src = reinterpret_cast<const char2 *>(static_cast<const int8_t *>(in) + (int64_t)p * ld);
-        fft<C, T, SPLIT, LMAP, false>(v, lds, src, a0, n_spectra, tw, tid);
-        if constexpr (Last<C>::REAL_VIA_LDS) real_split_lds<C, T, RL, SPLIT>(v, lds, tw2, tid);
-        else real_split_regs<C, T, RL>(v, tw2, tid);
+        fft<C, T, TH, SPLIT, LMAP, false>(v, lds, src, a0, n_spectra, tw, tid);
+        if constexpr (Last<C>::REAL_VIA_LDS) real_split_lds<C, T, TH, RL, SPLIT>(v, lds, tw2, tid);
+        else real_split_regs<C, T, TH, RL>(v, tw2, tid);
     } else {
-        fft<C, T, SPLIT, LMAP, NT>(v, lds, static_cast<const float2 *>(in) + (int64_t)p * ld, a0, n_spectra, tw,
+        fft<C, T, TH, SPLIT, LMAP, NT>(v, lds, static_cast<const float2 *>(in) + (int64_t)p * ld, a0, n_spectra, tw,
                                    tid);
     }
 
@@ -575,7 +584,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int q = 0; q < PT / RL; ++q) {
             int t, j;
-            bfly_index<C, T, RL, LMAP>(tid, q, t, j);
+            bfly_index<C, T, TH, RL, LMAP>(tid, q, t, j);
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int k = j + r * CR;
@@ -588,7 +597,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
             }
         }
         __syncthreads();
-        for (int c = tid; c < NCH; c += kThreads) {
+        for (int c = tid; c < NCH; c += TH) {
             const int row = c / CPR, x = c % CPR;
             const int pl = pl0 + row / C, k = row % C;
             const int a = a0 + x * (CH / ES);
@@ -604,7 +613,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 template <int PREC, int C, bool REAL>
 hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
                     const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, int tb0, hipStream_t stream) {
-    constexpr int T = kThreads * per_thread<C, PREC, REAL>() / C;
+    constexpr int TH = threads<C, PREC, REAL>();
+    constexpr int T = TH * per_thread<C, PREC, REAL>() / C;
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
     const int n_valid_pad = n_tb * TB;
@@ -612,7 +622,7 @@ hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const floa
     const int64_t n_work = (int64_t)N * groups;
     if (n_work <= 0 || n_work > (int64_t)1 << 30) return hipErrorInvalidValue;
     const int grid = (int)((n_work + 7) / 8) * 8;
-    hipLaunchKernelGGL((fengine_kernel<C, PREC, REAL>), dim3(grid), dim3(kThreads), 0, stream, in, ld, N,
+    hipLaunchKernelGGL((fengine_kernel<C, PREC, REAL>), dim3(grid), dim3(TH), 0, stream, in, ld, N,
                        n_spectra, n_valid_pad, (int)n_work, inv_scale, tw, tw2,
                        static_cast<uint8_t *>(spec), n_tb_cap, tb0);
     return hipGetLastError();
