@@ -26,6 +26,8 @@ Also reported on one JSON line:
                   type's MFMA peak;
   batched      -- 64 uneven sub-arrays: persistent batched X-engine vs
                   per-array launches, and the graph-replayed step;
+  config_steps -- whole F + X steps of the 256 x 2-input / 2048-channel (int8,
+                  FP16) and 512 x 2-input / 4096-channel (FP8) workloads;
   paper_workload -- 8-bit real samples, transform length 256, 128 to 3072
                   streams (the paper's own tests), FP32 and int8;
   cpu_baseline -- the oracle (float64 direct DFT + triple-loop correlation)
@@ -72,6 +74,8 @@ def parse():
                     help="graph replays per integration in the batched section")
     ap.add_argument("--cpu-channels", type=int, default=768)
     ap.add_argument("--no-equal-accuracy", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the whole F + X steps of the 2048- and 4096-channel workloads")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the 8-bit real-sample section (128 to 3072 streams, transform length 256)")
     ap.add_argument("--no-shapes", action="store_true",
@@ -290,6 +294,52 @@ def run_shapes(torch, corr, reps=3):
         log(f"rectangle 512x512 {prec}: X {ms:.3f} ms, {tc:.1f} TCMAC/s, {100 * 8 * tc / PEAK[prec]:.1f}% of MFMA peak")
         del out
         c.close()
+        torch.cuda.empty_cache()
+    return res
+
+
+def run_config_steps(torch, corr, synth, reps=3):
+    """Whole F + X steps (dump fused) of the larger configured workloads:
+    256 x 2 inputs, 2048 channels, 2048 spectra in int8 and FP16; 512 x 2
+    inputs, 4096 channels, 1024 spectra in FP8.  Voltages drawn on the device."""
+    res = {}
+    for name, precs in (("int8-256x2-c2048", ("int8", "fp16")), ("ska-512x2-c4096", ("fp8",))):
+        w = synth.WORKLOADS[name]
+        N, C, A = w.n_inputs, w.n_channels, w.n_integrate
+        volts = synth.voltages(w, device="cuda")
+        for prec in precs:
+            inv = torch.from_numpy(synth.inv_scale(w, prec)).to("cuda")
+            c = corr.Correlator(w.n_stations, w.n_pols, C, A, prec)
+            out = c.new_visibilities()
+            c.fengine(volts, A, inv)
+            c.xengine_dump(A, out)
+            ft, xt = Timer(torch), Timer(torch)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s_ = ft.start()
+                c.fengine(volts, A, inv)
+                ft.stop(s_)
+                s_ = xt.start()
+                c.xengine_dump(A, out)
+                xt.stop(s_)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+            f_ms, x_ms = ft.mean_ms(), xt.mean_ms()
+            cm = w.cmacs
+            res[f"{prec}/{name}"] = {
+                "inputs": N, "channels": C, "spectra": A, "step_ms": wall * 1e3, "fengine_ms": f_ms,
+                "xengine_ms": x_ms, "step_tcmacs": cm / wall / 1e12,
+                "xengine_tcmacs": cm / (x_ms * 1e-3) / 1e12,
+                "xengine_mfma_frac": 8 * cm / (x_ms * 1e-3) / 1e12 / PEAK[prec],
+                "fengine_hbm_gbs": N * A * C * (8 + 2 * ELEM_BYTES[prec]) / (f_ms * 1e-3) / 1e9}
+            log(f"config {name} {prec}: step {wall * 1e3:.2f} ms, F {f_ms:.2f} ms "
+                f"({res[f'{prec}/{name}']['fengine_hbm_gbs'] / 1e3:.2f} TB/s), X {x_ms:.2f} ms "
+                f"({100 * res[f'{prec}/{name}']['xengine_mfma_frac']:.1f}% of MFMA peak)")
+            del out
+            c.close()
+            torch.cuda.empty_cache()
+        del volts
         torch.cuda.empty_cache()
     return res
 
@@ -563,6 +613,10 @@ def main():
     if not args.no_shapes:
         shapes = run_shapes(torch, corr)
 
+    configs = None
+    if not args.no_configs:
+        configs = run_config_steps(torch, corr, synth)
+
     paper = None
     if not args.no_paper:
         paper = run_paper_workload(torch, corr, synth)
@@ -612,6 +666,7 @@ def main():
         "equal_accuracy": equal,
         "xengine_shapes": shapes,
         "batched": batched,
+        "config_steps": configs,
         "paper_workload": paper,
         "cpu_baseline": cpu,
     }

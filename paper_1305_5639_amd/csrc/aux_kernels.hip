@@ -14,9 +14,9 @@ template <typename T> __device__ __forceinline__ T zero_of() { return T(0); }
 // One thread per internal element (k, tb, p, plane, t): coalesced writes.
 template <typename T>
 __global__ void ingest_kernel(const T *__restrict__ src, T *__restrict__ spec, int C, int N, int n_spectra,
-                              int n_tb, int n_tb_cap) {
+                              int n_tb, SpecLayout lay) {
     constexpr int TB = kRowBytes / (int)sizeof(T);
-    const int64_t k_stride = channel_stride(n_tb_cap, N) / (int64_t)sizeof(T);
+    const int64_t k_stride = lay.ks / (int64_t)sizeof(T), t_stride = lay.ts / (int64_t)sizeof(T);
     const int64_t total = (int64_t)C * n_tb * N * 2 * TB;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -30,16 +30,16 @@ __global__ void ingest_kernel(const T *__restrict__ src, T *__restrict__ spec, i
         const int k = (int)(r / n_tb);
         const int a = tb * TB + t;
         const T v = a < n_spectra ? src[(((int64_t)a * C + k) * N + p) * 2 + pl] : zero_of<T>();
-        spec[k * k_stride + (((int64_t)tb * N + p) * 2 + pl) * TB + t] = v;
+        spec[tb * t_stride + k * k_stride + ((int64_t)p * 2 + pl) * TB + t] = v;
     }
 }
 
 // One thread per public element (a, k, p, plane): coalesced writes.
 template <typename T>
 __global__ void export_kernel(const T *__restrict__ spec, T *__restrict__ dst, int C, int N, int n_spectra,
-                              int n_tb_cap) {
+                              SpecLayout lay) {
     constexpr int TB = kRowBytes / (int)sizeof(T);
-    const int64_t k_stride = channel_stride(n_tb_cap, N) / (int64_t)sizeof(T);
+    const int64_t k_stride = lay.ks / (int64_t)sizeof(T), t_stride = lay.ts / (int64_t)sizeof(T);
     const int64_t total = (int64_t)n_spectra * C * N * 2;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -50,7 +50,7 @@ __global__ void export_kernel(const T *__restrict__ spec, T *__restrict__ dst, i
         const int k = (int)(r % C);
         const int a = (int)(r / C);
         const int tb = a / TB, t = a % TB;
-        dst[e] = spec[k * k_stride + (((int64_t)tb * N + p) * 2 + pl) * TB + t];
+        dst[e] = spec[tb * t_stride + k * k_stride + ((int64_t)p * 2 + pl) * TB + t];
     }
 }
 
@@ -135,40 +135,40 @@ int grid_for(int64_t n) {
 }
 
 template <typename T>
-hipError_t ingest_t(int C, int N, int n_spectra, int n_tb_cap, const void *src, void *spec, hipStream_t s) {
+hipError_t ingest_t(int C, int N, int n_spectra, SpecLayout lay, const void *src, void *spec, hipStream_t s) {
     constexpr int TB = kRowBytes / (int)sizeof(T);
     const int n_tb = (n_spectra + TB - 1) / TB;
     const int64_t total = (int64_t)C * n_tb * N * 2 * TB;
     hipLaunchKernelGGL(ingest_kernel<T>, dim3(grid_for(total)), dim3(kThreads), 0, s, static_cast<const T *>(src),
-                       static_cast<T *>(spec), C, N, n_spectra, n_tb, n_tb_cap);
+                       static_cast<T *>(spec), C, N, n_spectra, n_tb, lay);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t export_t(int C, int N, int n_spectra, int n_tb_cap, const void *spec, void *dst, hipStream_t s) {
+hipError_t export_t(int C, int N, int n_spectra, SpecLayout lay, const void *spec, void *dst, hipStream_t s) {
     const int64_t total = (int64_t)n_spectra * C * N * 2;
     hipLaunchKernelGGL(export_kernel<T>, dim3(grid_for(total)), dim3(kThreads), 0, s,
-                       static_cast<const T *>(spec), static_cast<T *>(dst), C, N, n_spectra, n_tb_cap);
+                       static_cast<const T *>(spec), static_cast<T *>(dst), C, N, n_spectra, lay);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_ingest(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *src, void *spec,
+hipError_t launch_ingest(int prec, int C, int N, int n_spectra, SpecLayout lay, const void *src, void *spec,
                          hipStream_t stream) {
     switch (elem_bytes(prec)) {
-    case 4: return ingest_t<uint32_t>(C, N, n_spectra, n_tb_cap, src, spec, stream);
-    case 2: return ingest_t<uint16_t>(C, N, n_spectra, n_tb_cap, src, spec, stream);
-    default: return ingest_t<uint8_t>(C, N, n_spectra, n_tb_cap, src, spec, stream);
+    case 4: return ingest_t<uint32_t>(C, N, n_spectra, lay, src, spec, stream);
+    case 2: return ingest_t<uint16_t>(C, N, n_spectra, lay, src, spec, stream);
+    default: return ingest_t<uint8_t>(C, N, n_spectra, lay, src, spec, stream);
     }
 }
 
-hipError_t launch_export(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *spec, void *dst,
+hipError_t launch_export(int prec, int C, int N, int n_spectra, SpecLayout lay, const void *spec, void *dst,
                          hipStream_t stream) {
     switch (elem_bytes(prec)) {
-    case 4: return export_t<uint32_t>(C, N, n_spectra, n_tb_cap, spec, dst, stream);
-    case 2: return export_t<uint16_t>(C, N, n_spectra, n_tb_cap, spec, dst, stream);
-    default: return export_t<uint8_t>(C, N, n_spectra, n_tb_cap, spec, dst, stream);
+    case 4: return export_t<uint32_t>(C, N, n_spectra, lay, spec, dst, stream);
+    case 2: return export_t<uint16_t>(C, N, n_spectra, lay, spec, dst, stream);
+    default: return export_t<uint8_t>(C, N, n_spectra, lay, spec, dst, stream);
     }
 }
 

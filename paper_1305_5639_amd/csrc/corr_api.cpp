@@ -25,6 +25,7 @@ using namespace corr;
 struct corr_ctx {
     corr_params p{};
     int N = 0, C = 0, prec = 0, TB = 0, n_tb_cap = 0;
+    SpecLayout lay{};                 // strides of the spectra buffer
     int64_t B = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -237,7 +238,7 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
     const int prec = params->precision;
     const int TB = time_block(prec);
     const int n_tb_cap = (params->n_integrate + TB - 1) / TB;
-    const size_t spec_bytes = (size_t)C * (size_t)channel_stride(n_tb_cap, N);
+    const size_t spec_bytes = (size_t)spec_buffer_bytes(C, N, n_tb_cap, elem_bytes(prec));
     const int64_t B = (int64_t)N * (N + 1) / 2;
     const size_t acc_bytes = (size_t)C * B * 8;
     const size_t small_bytes = (size_t)C * 8 + 2 * (size_t)C * 4;
@@ -259,6 +260,7 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
     h->prec = prec;
     h->TB = TB;
     h->n_tb_cap = n_tb_cap;
+    h->lay = spec_layout(C, N, n_tb_cap, elem_bytes(prec));
     h->B = B;
     h->stream = static_cast<hipStream_t>(hip_stream);
     h->spec_bytes = spec_bytes;
@@ -378,7 +380,7 @@ corr_status corr_fengine_at(corr_handle h, const void *d_volts, int64_t ld_sampl
     hipError_t e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
     e = launch_fengine(h->prec, h->C, h->N, static_cast<const float2 *>(d_volts), ld_samples, n_spectra,
-                       d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->spec, h->n_tb_cap,
+                       d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->spec, h->lay,
                        first_spectrum / time_block(h->prec), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine launch");
     h->n_held = first_spectrum + n_spectra;
@@ -410,7 +412,7 @@ corr_status corr_fengine_real8_at(corr_handle h, const int8_t *d_samples, int64_
     if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
     e = launch_fengine_real8(h->prec, h->C, h->N, d_samples, ld_samples, n_spectra,
                              d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->twiddle2n, h->spec,
-                             h->n_tb_cap, first_spectrum / time_block(h->prec), h->stream);
+                             h->lay, first_spectrum / time_block(h->prec), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine_real8 launch");
     h->n_held = first_spectrum + n_spectra;
     h->held_from_fengine = true;
@@ -447,7 +449,7 @@ static corr_status prepare_x(corr_ctx *h, const void *d_spectra, int32_t n_spect
     hipError_t e;
     const float *s2 = nullptr;
     if (d_spectra) {
-        e = launch_ingest(h->prec, h->C, h->N, n_spectra, h->n_tb_cap, d_spectra, h->spec, h->stream);
+        e = launch_ingest(h->prec, h->C, h->N, n_spectra, h->lay, d_spectra, h->spec, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "ingest launch");
         h->n_held = n_spectra;
         h->held_from_fengine = false;
@@ -470,8 +472,8 @@ corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra
     const float *s2 = nullptr;
     const corr_status st = prepare_x(h, d_spectra, n_spectra, d_inv_scale, &s2);
     if (st != CORR_OK) return st;
-    const hipError_t e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->n_tb_cap, h->spec,
-                                        s2, h->acc, h->acc, h->acc_zero ? 1 : 0, h->stream);
+    const hipError_t e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->spec, h->lay, s2,
+                                        h->acc, h->acc, h->acc_zero ? 1 : 0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
     h->acc_zero = false;
     h->n_integrated += n_spectra;
@@ -489,8 +491,8 @@ corr_status corr_xengine_dump(corr_handle h, const void *d_spectra, int32_t n_sp
     const float *s2 = nullptr;
     const corr_status st = prepare_x(h, d_spectra, n_spectra, d_inv_scale, &s2);
     if (st != CORR_OK) return st;
-    const hipError_t e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->n_tb_cap, h->spec,
-                                        s2, d_dst, h->acc, h->acc_zero ? 1 : 0, h->stream);
+    const hipError_t e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->spec, h->lay, s2,
+                                        d_dst, h->acc, h->acc_zero ? 1 : 0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
     h->acc_zero = true;                                  // the integration ends here: reset
     h->n_integrated = 0;
@@ -512,8 +514,8 @@ corr_status corr_xengine_rect(corr_handle h, int32_t i0, int32_t ni, int32_t j0,
     if (n_spectra > h->n_held) return fail(h, CORR_E_STATE, "n_spectra exceeds the spectra held");
     if (h->prec == P_INT8 && n_spectra > CORR_INT8_MAX_INTEGRATE)
         return fail(h, CORR_E_OVERFLOW, "int8 rectangle over more than 66572 spectra");
-    const hipError_t e = launch_xengine_rect(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->n_tb_cap,
-                                             h->spec, x_scale(h), d_out, accumulate ? 0 : 1, i0, ni, j0, nj,
+    const hipError_t e = launch_xengine_rect(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->spec,
+                                             h->lay, x_scale(h), d_out, accumulate ? 0 : 1, i0, ni, j0, nj,
                                              h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "rectangle launch");
     h->err.clear();
@@ -584,7 +586,7 @@ corr_status corr_copy_spectra(corr_handle h, void *dst, int32_t dst_on_device) {
         if ((e = hipMalloc(&tmp, bytes)) != hipSuccess) return hip_fail(h, e, "hipMalloc spectra staging");
         target = tmp;
     }
-    e = launch_export(h->prec, h->C, h->N, h->n_held, h->n_tb_cap, h->spec, target, h->stream);
+    e = launch_export(h->prec, h->C, h->N, h->n_held, h->lay, h->spec, target, h->stream);
     if (e == hipSuccess && !dst_on_device) {
         e = hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -641,11 +643,10 @@ corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile_out) {
     int best = 0;
     for (int c : cand) {
         float ms = 0;
-        e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->n_tb_cap, h->spec, x_scale(h), tmp, tmp, 1,
-                           h->stream);
+        e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->spec, h->lay, x_scale(h), tmp, tmp, 1, h->stream);
         for (int r = 0; e == hipSuccess && r < 3; ++r) {
             (void)hipEventRecord(ev[0], h->stream);
-            e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->n_tb_cap, h->spec, x_scale(h), tmp, tmp, 1,
+            e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->spec, h->lay, x_scale(h), tmp, tmp, 1,
                                h->stream);
             (void)hipEventRecord(ev[1], h->stream);
             if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
@@ -699,7 +700,8 @@ corr_status corr_create_batched(const corr_params *params, int32_t n, void *hip_
             return fail(nullptr, CORR_E_UNSUPPORTED, "all sub-arrays must share one precision");
         const int64_t N = n_inputs(&params[i]);
         const int TB = time_block(params[i].precision);
-        need += (uint64_t)params[i].n_channels * channel_stride((params[i].n_integrate + TB - 1) / TB, (int)N) +
+        need += (uint64_t)spec_buffer_bytes(params[i].n_channels, (int)N, (params[i].n_integrate + TB - 1) / TB,
+                                            elem_bytes(params[i].precision)) +
                 (uint64_t)params[i].n_channels * (N * (N + 1) / 2) * 8;
     }
     if (params[0].device_mem_cap && need > params[0].device_mem_cap)
@@ -789,7 +791,8 @@ corr_status corr_xengine_batched(corr_batch_handle b, const int32_t *n_spectra) 
             x.spec = static_cast<const uint8_t *>(h->spec);
             x.acc = h->acc;
             x.scale2 = x_scale(h);
-            x.k_stride = channel_stride(h->n_tb_cap, h->N);
+            x.k_stride = h->lay.ks;
+            x.tb_stride = h->lay.ts;
             x.B = h->B;
             x.C = h->C;
             x.N = h->N;

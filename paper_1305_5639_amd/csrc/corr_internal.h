@@ -1,16 +1,18 @@
 // Internal declarations shared by the C-ABI layer and the HIP kernels.
 //
-// Spectra buffer layout (device, library-owned), "time-blocked planar":
+// Spectra buffer layout (device, library-owned), "time-blocked planar": the
+// 128-byte row of (channel k, time block tb, input p) -- plane 0 (real) then
+// plane 1 (imaginary), TB spectra each, 64 bytes per plane -- sits at
 //
-//   spec[k][tb][p][plane][TB]      k  : channel            [0, C), stride
-//                                       channel_stride() bytes
-//                                  tb : time block         [0, n_tb)
-//                                  p  : input              [0, N)
-//                                  plane: 0 = real, 1 = imaginary
-//                                  TB : spectra per block (64 bytes per row)
+//   spec + k * ks + tb * ts + p * 128
 //
-// so that, for one channel and one time block, the rows of every input are
-// one contiguous run of N * 128 bytes.  An X-engine tile of 128 inputs reads a
+// with one of two stride pairs (SpecLayout, chosen per handle):
+//   channel-major    [k][tb][p]: ts = N * 128, ks = n_tb_cap * N * 128 + pad
+//   time-block-major [tb][k][p]: ks = N * 128 + pad, ts = C * ks
+// Either way the rows of every input for one channel and one time block are
+// one contiguous run of N * 128 bytes.  Time-block-major keeps the rows one
+// F-engine workgroup writes (one input, every channel, one time block) within
+// C * ks bytes however long the integration.  An X-engine tile of 128 inputs reads a
 // contiguous 16 KB slab per time block, and each MFMA fragment (a row's K
 // consecutive spectra of one plane) is a 16-byte vector.  Entries of the last
 // time block beyond the valid spectra are zero, so every block can be
@@ -30,14 +32,32 @@ enum Prec : int { P_FP32 = 0, P_FP16 = 1, P_FP8 = 2, P_INT8 = 3 };
 
 // Bytes per (input, plane) row of one time block.
 constexpr int kRowBytes = 64;
-// Bytes added after each channel's slab of the spectra buffer.  Without it
-// the channel stride is a large power of two and the F-engine's transposing
-// stores (one per channel) all land in the same HBM channel.
+// Bytes added after each channel's slab of a time block.  Without it the
+// channel stride is a power of two for power-of-two N and the F-engine's
+// transposing stores (one per channel) all land in the same HBM channel.
 constexpr int kChannelPad = 256;
 
-// Byte stride between channels of the spectra buffer.
-__host__ __device__ inline int64_t channel_stride(int n_tb_cap, int N) {
-    return (int64_t)n_tb_cap * N * 2 * kRowBytes + kChannelPad;
+struct SpecLayout {
+    int64_t ks;                       // bytes between channels
+    int64_t ts;                       // bytes between time blocks
+};
+// Measured on the MI355X: time-block-major is faster for the larger spectra
+// buffers and for many inputs (2048 channels x 512 inputs x 2048 spectra:
+// int8 F-engine 12.2 -> 9.3 ms; 4096 x 1024 x 1024 FP8: 28.7 -> 18.1 ms;
+// 128 channels x 2048 inputs: F 0.61 -> 0.55 ms, X 1.37 -> 1.26 ms), and
+// slower for the 1024 x 256 x 1000 case (FP32 F-engine 1.13 -> 1.47 ms).
+inline SpecLayout spec_layout(int C, int N, int n_tb_cap, int elem) {
+    const int64_t row = (int64_t)N * 2 * kRowBytes;
+    (void)n_tb_cap;
+    const bool tb_major = N >= 512 || C >= 2048 || C * elem < 1024;
+    if (tb_major) return {row + kChannelPad, (int64_t)C * (row + kChannelPad)};
+    return {(int64_t)n_tb_cap * row + kChannelPad, row};
+}
+// Bytes of the spectra buffer: every row of n_tb_cap time blocks, plus padding.
+inline int64_t spec_buffer_bytes(int C, int N, int n_tb_cap, int elem) {
+    const SpecLayout l = spec_layout(C, N, n_tb_cap, elem);
+    const int64_t a = (int64_t)(C - 1) * l.ks + (int64_t)(n_tb_cap - 1) * l.ts + (int64_t)N * 2 * kRowBytes;
+    return a + kChannelPad;
 }
 
 inline int elem_bytes(int prec) { return prec == P_FP32 ? 4 : (prec == P_FP16 ? 2 : 1); }
@@ -52,14 +72,14 @@ inline int time_block(int prec) { return kRowBytes / elem_bytes(prec); }
 // spectra land from time block first_tb of the buffer on.
 hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld,
                           int n_spectra, const float *inv_scale, const float2 *twiddle,
-                          void *spec, int n_tb_cap, int first_tb, hipStream_t stream);
+                          void *spec, SpecLayout lay, int first_tb, hipStream_t stream);
 
 // F-engine on int8 real samples (Section 5): block a of row p is the 2C bytes
 // samples[p*ld + a*2C ..]; channels k < C of its length-2C DFT.  twiddle2n[k]
 // = exp(-j pi k / C), k < C.  ld even.
 hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, int64_t ld, int n_spectra,
                                 const float *inv_scale, const float2 *twiddle, const float2 *twiddle2n,
-                                void *spec, int n_tb_cap, int first_tb, hipStream_t stream);
+                                void *spec, SpecLayout lay, int first_tb, hipStream_t stream);
 
 // X-engine: accumulate Eq. 2 over the first n_spectra spectra of the spectra
 // buffer into acc (spectra past n_spectra in the last time block are masked to
@@ -68,14 +88,13 @@ hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, i
 // products.  first_call = 1 writes instead of read-modify-write.  The sums so
 // far are read from acc_in (acc itself, or the accumulators when acc is a
 // dump destination in the accumulator layout).
-hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
-                          const float *scale2, void *acc, const void *acc_in, int first_call,
-                          hipStream_t stream);
+hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
+                          const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream);
 
 // Rectangle X-engine: rows [r0, r0 + ni) against columns [c0, c0 + nj) of the
 // held spectra (disjoint ranges), into out [C][ni][nj] (re, im) pairs, written
 // when first_call, else added to.
-hipError_t launch_xengine_rect(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+hipError_t launch_xengine_rect(int prec, int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
                                const float *scale2, void *out, int first_call, int r0, int ni, int c0, int nj,
                                hipStream_t stream);
 
@@ -92,7 +111,8 @@ struct XDesc {
     const uint8_t *spec;
     void *acc;
     const float *scale2;
-    int64_t k_stride;
+    int64_t k_stride;                 // SpecLayout::ks
+    int64_t tb_stride;                // SpecLayout::ts
     int64_t B;
     int64_t qbegin[kXcds];            // offset of this sub-array's items in each XCD's queue
     int C, N, n_tb, tv, tile, n_tiles, first_call, pad;
@@ -121,9 +141,9 @@ hipError_t launch_xengine_batched(int prec, const XQueue *d_plan, const XDesc *d
 
 // Public [A][C][N][2] spectra <-> internal layout (ingest zero-fills the tail
 // of the last time block).
-hipError_t launch_ingest(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *src,
+hipError_t launch_ingest(int prec, int C, int N, int n_spectra, SpecLayout lay, const void *src,
                          void *spec, hipStream_t stream);
-hipError_t launch_export(int prec, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+hipError_t launch_export(int prec, int C, int N, int n_spectra, SpecLayout lay, const void *spec,
                          void *dst, hipStream_t stream);
 
 // Dump conversion from the lower-triangle channel-major accumulators into a

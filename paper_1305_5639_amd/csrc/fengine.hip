@@ -499,8 +499,8 @@ __global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_w
     PREC == P_FP32 || (REAL && Last<C>::REAL_VIA_LDS) || per_thread<C, PREC, REAL>() == 64 ? 2 : 3))) void fengine_kernel(
     const void *__restrict__ in, int64_t ld, int N, int n_spectra, int n_valid_pad,
     int n_work, const float *__restrict__ inv_scale,
-    const float2 *__restrict__ tw, const float2 *__restrict__ tw2, uint8_t *__restrict__ spec, int n_tb_cap,
-    int tb0) {
+    const float2 *__restrict__ tw, const float2 *__restrict__ tw2, uint8_t *__restrict__ spec, int64_t k_stride,
+    int64_t t_stride, int tb0) {
     using E = typename Elem<PREC>::T;
     constexpr int TH = threads<C, PREC, REAL>();      // threads per workgroup
     constexpr int PT = per_thread<C, PREC, REAL>();   // complex values per thread
@@ -576,7 +576,6 @@ __global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_w
     using V = typename Bytes<CH>::T;
     constexpr int CPR = S / CH;                        // chunks per staged row
     constexpr int NCH = NPL * C * CPR;
-    const int64_t k_stride = channel_stride(n_tb_cap, N);
     uint8_t *stage = reinterpret_cast<uint8_t *>(lds);
 #pragma unroll
     for (int pl0 = 0; pl0 < 2; pl0 += NPL) {
@@ -603,7 +602,7 @@ __global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_w
             const int a = a0 + x * (CH / ES);
             if (a >= n_valid_pad) continue;
             const int tb = tb0 + a / TB, within = a % TB;
-            uint8_t *dst = spec + (int64_t)k * k_stride + ((int64_t)tb * N + p) * (2 * kRowBytes) +
+            uint8_t *dst = spec + (int64_t)tb * t_stride + (int64_t)k * k_stride + (int64_t)p * (2 * kRowBytes) +
                            pl * kRowBytes + within * ES;
             *reinterpret_cast<V *>(dst) = *reinterpret_cast<const V *>(stage + c * CH);
         }
@@ -612,7 +611,7 @@ __global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_w
 
 template <int PREC, int C, bool REAL>
 hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                    const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, int tb0, hipStream_t stream) {
+                    const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, int tb0, hipStream_t stream) {
     constexpr int TH = threads<C, PREC, REAL>();
     constexpr int T = TH * per_thread<C, PREC, REAL>() / C;
     const int TB = time_block(PREC);
@@ -624,15 +623,15 @@ hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const floa
     const int grid = (int)((n_work + 7) / 8) * 8;
     hipLaunchKernelGGL((fengine_kernel<C, PREC, REAL>), dim3(grid), dim3(TH), 0, stream, in, ld, N,
                        n_spectra, n_valid_pad, (int)n_work, inv_scale, tw, tw2,
-                       static_cast<uint8_t *>(spec), n_tb_cap, tb0);
+                       static_cast<uint8_t *>(spec), lay.ks, lay.ts, tb0);
     return hipGetLastError();
 }
 
 template <int PREC, bool REAL>
 hipError_t launch_p(int C, int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                    const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, int tb0, hipStream_t stream) {
+                    const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, int tb0, hipStream_t stream) {
 #define CORR_FENGINE_CASE(c)                                                                            \
-    case c: return launch_c<PREC, c, REAL>(N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
+    case c: return launch_c<PREC, c, REAL>(N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
     switch (C) {
         CORR_FENGINE_CASE(16)
         CORR_FENGINE_CASE(32)
@@ -651,12 +650,12 @@ hipError_t launch_p(int C, int N, const void *in, int64_t ld, int n_spectra, con
 
 template <bool REAL>
 hipError_t launch_any(int prec, int C, int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                      const float2 *tw, const float2 *tw2, void *spec, int n_tb_cap, int tb0, hipStream_t stream) {
+                      const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, int tb0, hipStream_t stream) {
     switch (prec) {
-    case P_FP32: return launch_p<P_FP32, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
-    case P_FP16: return launch_p<P_FP16, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
-    case P_FP8: return launch_p<P_FP8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
-    case P_INT8: return launch_p<P_INT8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, n_tb_cap, tb0, stream);
+    case P_FP32: return launch_p<P_FP32, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
+    case P_FP16: return launch_p<P_FP16, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
+    case P_FP8: return launch_p<P_FP8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
+    case P_INT8: return launch_p<P_INT8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -664,17 +663,17 @@ hipError_t launch_any(int prec, int C, int N, const void *in, int64_t ld, int n_
 }  // namespace
 
 hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld, int n_spectra,
-                          const float *inv_scale, const float2 *twiddle, void *spec, int n_tb_cap, int first_tb,
+                          const float *inv_scale, const float2 *twiddle, void *spec, SpecLayout lay, int first_tb,
                           hipStream_t stream) {
-    return launch_any<false>(prec, C, N, volts, ld, n_spectra, inv_scale, twiddle, nullptr, spec, n_tb_cap, first_tb,
+    return launch_any<false>(prec, C, N, volts, ld, n_spectra, inv_scale, twiddle, nullptr, spec, lay, first_tb,
                              stream);
 }
 
 hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, int64_t ld, int n_spectra,
                                 const float *inv_scale, const float2 *twiddle, const float2 *twiddle2n, void *spec,
-                                int n_tb_cap, int first_tb, hipStream_t stream) {
-    return launch_any<true>(prec, C, N, samples, ld, n_spectra, inv_scale, twiddle, twiddle2n, spec, n_tb_cap,
-                            first_tb, stream);
+                                SpecLayout lay, int first_tb, hipStream_t stream) {
+    return launch_any<true>(prec, C, N, samples, ld, n_spectra, inv_scale, twiddle, twiddle2n, spec, lay, first_tb,
+                            stream);
 }
 
 }  // namespace corr

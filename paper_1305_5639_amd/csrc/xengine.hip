@@ -241,7 +241,8 @@ struct OutMap {
 // they only feed outputs that are not written.  In the last time block,
 // spectra past the valid count are zeroed in LDS once it lands.
 template <int PREC, int TILE, bool RECT = false>
-__device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ base_k, int N, int n_tb, int tv,
+__device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ base_k, int64_t t_stride, int N,
+                                     int n_tb, int tv,
                                      int I0, int J0, int k, const float *__restrict__ scale2,
                                      void *__restrict__ acc_out, const void *acc_in, int64_t B, int first_call,
                                      int tid,
@@ -280,7 +281,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)smem;
     gu8 *const gbase = (gu8 *)base_k;
     auto issue = [&](int t) {
-        gu8 *src = gbase + (int64_t)t * N * RB;
+        gu8 *src = gbase + (int64_t)t * t_stride;
         const uint32_t dst = lds0 + (uint32_t)((t & 1) * STG);
 #pragma unroll
         for (int j = 0; j < L; ++j)
@@ -423,8 +424,8 @@ __device__ __forceinline__ void tri_block(int t, int &bi, int &bj) {
 template <int PREC, int TILE>
 __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(4))) void xengine_kernel(
     const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
-    int64_t k_stride, const float *__restrict__ scale2, void *__restrict__ acc_out, const void *acc_in, int64_t B,
-    int first_call) {
+    int64_t k_stride, int64_t t_stride, const float *__restrict__ scale2, void *__restrict__ acc_out,
+    const void *acc_in, int64_t B, int first_call) {
     __shared__ __attribute__((aligned(16))) uint8_t smem[ring_bytes(TILE)];
     const int per = (n_work + 7) / 8;
     const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -432,8 +433,8 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
     const int k = w / n_tiles;
     int bi, bj;
     tri_block(w % n_tiles, bi, bj);
-    tile<PREC, TILE>(smem, spec + (int64_t)k * k_stride, N, n_tb, tv, bi * TILE, bj * TILE, k, scale2, acc_out,
-                     acc_in, B, first_call, threadIdx.x);
+    tile<PREC, TILE>(smem, spec + (int64_t)k * k_stride, t_stride, N, n_tb, tv, bi * TILE, bj * TILE, k, scale2,
+                     acc_out, acc_in, B, first_call, threadIdx.x);
 }
 
 // Rectangle X-engine: rows [r0, r0 + ni) against columns [c0, c0 + nj) in
@@ -441,14 +442,15 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
 template <int PREC, int TILE>
 __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(4))) void xengine_rect_kernel(
     const uint8_t *__restrict__ spec, int N, int nbi, int nbj, int n_work, int n_tb, int tv, int64_t k_stride,
-    const float *__restrict__ scale2, void *__restrict__ out, int64_t B, int first_call, OutMap om) {
+    int64_t t_stride, const float *__restrict__ scale2, void *__restrict__ out, int64_t B, int first_call, OutMap om) {
     __shared__ __attribute__((aligned(16))) uint8_t smem[ring_bytes(TILE)];
     const int per = (n_work + 7) / 8;
     const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (w >= n_work) return;
     const int nb = nbi * nbj;
     const int k = w / nb, bi = (w % nb) / nbj, bj = w % nbj;
-    tile<PREC, TILE, true>(smem, spec + (int64_t)k * k_stride, N, n_tb, tv, om.r0 + bi * TILE, om.c0 + bj * TILE, k,
+    tile<PREC, TILE, true>(smem, spec + (int64_t)k * k_stride, t_stride, N, n_tb, tv, om.r0 + bi * TILE,
+                           om.c0 + bj * TILE, k,
                            scale2, out, out, B, first_call, threadIdx.x, om);
 }
 
@@ -500,7 +502,8 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
             // across it (which cost registers and occupancy)
             int t = tid;
             asm volatile("" : "+v"(t));
-            tile<PREC, TILE>(smem, d.spec + (int64_t)k * d.k_stride, d.N, d.n_tb, d.tv, bi * TILE, bj * TILE, k,
+            tile<PREC, TILE>(smem, d.spec + (int64_t)k * d.k_stride, d.tb_stride, d.N, d.n_tb, d.tv, bi * TILE,
+                             bj * TILE, k,
                              d.scale2, d.acc, d.acc, d.B, d.first_call, t);
             if (tid == 0) s_item = next;
             __syncthreads();                            // also: every wave is done with smem
@@ -513,8 +516,8 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
 __global__ void reset_counters_kernel(unsigned int *counter) { counter[threadIdx.x * kCounterStride] = 0u; }
 
 template <int PREC, int TILE>
-hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
-                    void *acc, const void *acc_in, int first_call, hipStream_t stream) {
+hipError_t launch_x(int C, int N, int n_spectra, const void *spec, SpecLayout lay,
+                    const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream) {
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
     const int tv = n_spectra - (n_tb - 1) * TB;
@@ -523,27 +526,25 @@ hipError_t launch_x(int C, int N, int n_spectra, int n_tb_cap, const void *spec,
     const int64_t n_work = (int64_t)C * n_tiles;
     if (n_tb <= 0 || n_work <= 0 || n_work > ((int64_t)1 << 30)) return hipErrorInvalidValue;
     const int grid = (int)((n_work + 7) / 8) * 8;
-    const int64_t k_stride = channel_stride(n_tb_cap, N);
     const int64_t B = (int64_t)N * (N + 1) / 2;
     hipLaunchKernelGGL((xengine_kernel<PREC, TILE>), dim3(grid), dim3(WaveGrid<TILE>::THREADS), 0, stream,
-                       static_cast<const uint8_t *>(spec), N, n_tiles, (int)n_work, n_tb, tv, k_stride,
+                       static_cast<const uint8_t *>(spec), N, n_tiles, (int)n_work, n_tb, tv, lay.ks, lay.ts,
                        scale2, acc, acc_in, B, first_call);
     return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t launch_xp(int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
-                     void *acc, const void *acc_in, int first_call, hipStream_t stream) {
-    if (tile == 64) return launch_x<PREC, 64>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
-    if (tile == 128)
-        return launch_x<PREC, 128>(C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
+hipError_t launch_xp(int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
+                     const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream) {
+    if (tile == 64) return launch_x<PREC, 64>(C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, stream);
+    if (tile == 128) return launch_x<PREC, 128>(C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, stream);
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 template <int PREC, int TILE>
-hipError_t launch_rect_t(int C, int N, int n_spectra, int n_tb_cap, const void *spec, const float *scale2,
+hipError_t launch_rect_t(int C, int N, int n_spectra, const void *spec, SpecLayout lay, const float *scale2,
                          void *out, int first_call, int r0, int ni, int c0, int nj, hipStream_t stream) {
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
@@ -555,41 +556,43 @@ hipError_t launch_rect_t(int C, int N, int n_spectra, int n_tb_cap, const void *
     const int grid = (int)((n_work + 7) / 8) * 8;
     hipLaunchKernelGGL((xengine_rect_kernel<PREC, TILE>), dim3(grid), dim3(WaveGrid<TILE>::THREADS), 0, stream,
                        static_cast<const uint8_t *>(spec), N, nbi, nbj, (int)n_work, n_tb, tv,
-                       channel_stride(n_tb_cap, N), scale2, out, (int64_t)ni * nj, first_call,
+                       lay.ks, lay.ts, scale2, out, (int64_t)ni * nj, first_call,
                        OutMap{r0, r0 + ni, c0, c0 + nj});
     return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t launch_rect_p(int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+hipError_t launch_rect_p(int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
                          const float *scale2, void *out, int first_call, int r0, int ni, int c0, int nj,
                          hipStream_t stream) {
     if (tile == 64)
-        return launch_rect_t<PREC, 64>(C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+        return launch_rect_t<PREC, 64>(C, N, n_spectra, spec, lay, scale2, out, first_call, r0, ni, c0, nj, stream);
     if (tile == 128)
-        return launch_rect_t<PREC, 128>(C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+        return launch_rect_t<PREC, 128>(C, N, n_spectra, spec, lay, scale2, out, first_call, r0, ni, c0, nj, stream);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_xengine_rect(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+hipError_t launch_xengine_rect(int prec, int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
                                const float *scale2, void *out, int first_call, int r0, int ni, int c0, int nj,
                                hipStream_t stream) {
     switch (prec) {
-    case P_FP32: return launch_rect_p<P_FP32>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
-    case P_FP16: return launch_rect_p<P_FP16>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
-    case P_FP8: return launch_rect_p<P_FP8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
-    case P_INT8: return launch_rect_p<P_INT8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, out, first_call, r0, ni, c0, nj, stream);
+    case P_FP32: return launch_rect_p<P_FP32>(tile, C, N, n_spectra, spec, lay, scale2, out, first_call, r0, ni, c0, nj, stream);
+    case P_FP16: return launch_rect_p<P_FP16>(tile, C, N, n_spectra, spec, lay, scale2, out, first_call, r0, ni, c0, nj, stream);
+    case P_FP8: return launch_rect_p<P_FP8>(tile, C, N, n_spectra, spec, lay, scale2, out, first_call, r0, ni, c0, nj, stream);
+    case P_INT8: return launch_rect_p<P_INT8>(tile, C, N, n_spectra, spec, lay, scale2, out, first_call, r0, ni, c0, nj, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, int n_tb_cap, const void *spec,
+hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
                           const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream) {
+#define CORR_X_ARGS tile, C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, stream
     switch (prec) {
-    case P_FP32: return launch_xp<P_FP32>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
-    case P_FP16: return launch_xp<P_FP16>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
-    case P_FP8: return launch_xp<P_FP8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
-    case P_INT8: return launch_xp<P_INT8>(tile, C, N, n_spectra, n_tb_cap, spec, scale2, acc, acc_in, first_call, stream);
+    case P_FP32: return launch_xp<P_FP32>(CORR_X_ARGS);
+    case P_FP16: return launch_xp<P_FP16>(CORR_X_ARGS);
+    case P_FP8: return launch_xp<P_FP8>(CORR_X_ARGS);
+    case P_INT8: return launch_xp<P_INT8>(CORR_X_ARGS);
+#undef CORR_X_ARGS
     default: return hipErrorInvalidValue;
     }
 }
