@@ -1,7 +1,7 @@
 // Data-movement kernels around the two engines: caller spectra in and out of
 // the time-blocked planar layout, dump layout/order conversion, the s_k^2
-// table and a zero fill.  None of these is on the F -> X hot path; they are
-// plain coalesced-write element maps.
+// table and a zero fill.  None of these is on the F -> X hot path; the
+// spectra moves are LDS-tiled transposes, the rest coalesced element maps.
 #include "corr_internal.h"
 
 namespace corr {
@@ -9,48 +9,98 @@ namespace {
 
 constexpr int kThreads = 256;
 
-template <typename T> __device__ __forceinline__ T zero_of() { return T(0); }
 
-// One thread per internal element (k, tb, p, plane, t): coalesced writes.
+// Caller spectra <-> held rows.  For channel k and time block tb, the TB
+// public rows a = tb*TB + t hold the 2N columns (2p + plane) of that channel
+// contiguously; the held layout wants each column's TB values contiguous (one
+// 64-byte plane row).  That is a TB x 2N transpose per (k, tb).  One
+// workgroup moves a tile of kCols columns: TB public segments of kCols * ES
+// bytes <-> kCols held rows of 64 bytes, 16 KB either way, through LDS.  Both
+// sides move 16-byte vectors; the LDS row of public row t stores its 16-byte
+// chunks XOR-swizzled by the held vector t falls in, so the gathers of one
+// wave (16 columns x 4 held vectors) hit distinct banks.
+constexpr int kCols = 256;
+
 template <typename T>
-__global__ void ingest_kernel(const T *__restrict__ src, T *__restrict__ spec, int C, int N, int n_spectra,
-                              int n_tb, SpecLayout lay) {
-    constexpr int TB = kRowBytes / (int)sizeof(T);
-    const int64_t k_stride = lay.ks / (int64_t)sizeof(T), t_stride = lay.ts / (int64_t)sizeof(T);
-    const int64_t total = (int64_t)C * n_tb * N * 2 * TB;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int t = (int)(e % TB);
-        int64_t r = e / TB;
-        const int pl = (int)(r % 2);
-        r /= 2;
-        const int p = (int)(r % N);
-        r /= N;
-        const int tb = (int)(r % n_tb);
-        const int k = (int)(r / n_tb);
-        const int a = tb * TB + t;
-        const T v = a < n_spectra ? src[(((int64_t)a * C + k) * N + p) * 2 + pl] : zero_of<T>();
-        spec[tb * t_stride + k * k_stride + ((int64_t)p * 2 + pl) * TB + t] = v;
-    }
+__device__ __forceinline__ int lds_elem(int t, int j) {
+    constexpr int ES = (int)sizeof(T), VE = 16 / ES, W = kCols * ES;
+    const int byte = j * ES, chunk = byte >> 4;
+    const int tg = (t / VE) & 3;
+    return t * W + ((chunk ^ (tg * ES)) << 4) + (byte & 15);
 }
 
-// One thread per public element (a, k, p, plane): coalesced writes.
-template <typename T>
-__global__ void export_kernel(const T *__restrict__ spec, T *__restrict__ dst, int C, int N, int n_spectra,
-                              SpecLayout lay) {
-    constexpr int TB = kRowBytes / (int)sizeof(T);
-    const int64_t k_stride = lay.ks / (int64_t)sizeof(T), t_stride = lay.ts / (int64_t)sizeof(T);
-    const int64_t total = (int64_t)n_spectra * C * N * 2;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int pl = (int)(e % 2);
-        int64_t r = e / 2;
-        const int p = (int)(r % N);
-        r /= N;
-        const int k = (int)(r % C);
-        const int a = (int)(r / C);
-        const int tb = a / TB, t = a % TB;
-        dst[e] = spec[tb * t_stride + k * k_stride + ((int64_t)p * 2 + pl) * TB + t];
+// INGEST: public src -> held dst (the tail of the last block zero-filled);
+// else held src -> public dst.  VEC: public rows 16-byte aligned (2N * ES a
+// multiple of 16, base aligned), so public segments move as vectors.
+template <typename T, bool INGEST, bool VEC>
+__global__ __launch_bounds__(kThreads) void relayout_kernel(const uint8_t *__restrict__ src,
+                                                             uint8_t *__restrict__ dst, int C, int N,
+                                                             int n_spectra, int n_tb, int n_cc, SpecLayout lay) {
+    constexpr int ES = (int)sizeof(T), TB = kRowBytes / ES, VE = 16 / ES, W = kCols * ES;
+    constexpr int PUB_VECS = TB * (W / 16);             // 1024 either side
+    __shared__ __align__(16) uint8_t lds[TB * W];
+    const int64_t g = blockIdx.x;
+    const int cc = (int)(g % n_cc);
+    const int tb = (int)((g / n_cc) % n_tb);
+    const int k = (int)(g / ((int64_t)n_cc * n_tb));
+    const int cols = 2 * N, c_base = cc * kCols;
+    const int64_t pub_row = (int64_t)cols * ES;         // bytes per public (a, k) row
+    uint8_t *held = (INGEST ? dst : const_cast<uint8_t *>(src)) + (int64_t)tb * lay.ts + (int64_t)k * lay.ks;
+
+    auto pub_addr = [&](int t, int col) -> int64_t {
+        return ((int64_t)(tb * TB + t) * C + k) * pub_row + (int64_t)col * ES;
+    };
+    if (INGEST) {
+        for (int i = threadIdx.x; i < PUB_VECS; i += kThreads) {
+            const int t = i / (W / 16), c = i % (W / 16);
+            const int a = tb * TB + t, col0 = c_base + c * VE;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (a < n_spectra && col0 < cols) {
+                if (VEC && col0 + VE <= cols) {
+                    v = *reinterpret_cast<const uint4 *>(src + pub_addr(t, col0));
+                } else {
+                    T e[VE];
+                    for (int u = 0; u < VE; ++u)
+                        e[u] = col0 + u < cols ? *reinterpret_cast<const T *>(src + pub_addr(t, col0 + u)) : T(0);
+                    __builtin_memcpy(&v, e, 16);
+                }
+            }
+            *reinterpret_cast<uint4 *>(lds + lds_elem<T>(t, c * VE)) = v;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kCols * 4; i += kThreads) {
+            const int j = i >> 2, hv = i & 3, col = c_base + j;
+            if (col >= cols) continue;
+            T e[VE];
+            for (int u = 0; u < VE; ++u) e[u] = *reinterpret_cast<const T *>(lds + lds_elem<T>(hv * VE + u, j));
+            uint4 v;
+            __builtin_memcpy(&v, e, 16);
+            *reinterpret_cast<uint4 *>(held + (int64_t)col * kRowBytes + hv * 16) = v;
+        }
+    } else {
+        for (int i = threadIdx.x; i < kCols * 4; i += kThreads) {
+            const int j = i >> 2, hv = i & 3, col = c_base + j;
+            if (col >= cols) continue;
+            const uint4 v = *reinterpret_cast<const uint4 *>(held + (int64_t)col * kRowBytes + hv * 16);
+            T e[VE];
+            __builtin_memcpy(e, &v, 16);
+            for (int u = 0; u < VE; ++u) *reinterpret_cast<T *>(lds + lds_elem<T>(hv * VE + u, j)) = e[u];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < PUB_VECS; i += kThreads) {
+            const int t = i / (W / 16), c = i % (W / 16);
+            const int a = tb * TB + t, col0 = c_base + c * VE;
+            if (a >= n_spectra || col0 >= cols) continue;
+            const uint4 v = *reinterpret_cast<const uint4 *>(lds + lds_elem<T>(t, c * VE));
+            if (VEC && col0 + VE <= cols) {
+                *reinterpret_cast<uint4 *>(dst + pub_addr(t, col0)) = v;
+            } else {
+                T e[VE];
+                __builtin_memcpy(e, &v, 16);
+                for (int u = 0; u < VE && col0 + u < cols; ++u)
+                    *reinterpret_cast<T *>(dst + pub_addr(t, col0 + u)) = e[u];
+            }
+        }
     }
 }
 
@@ -134,21 +184,24 @@ int grid_for(int64_t n) {
     return (int)g;
 }
 
-template <typename T>
-hipError_t ingest_t(int C, int N, int n_spectra, SpecLayout lay, const void *src, void *spec, hipStream_t s) {
+template <typename T, bool INGEST>
+hipError_t relayout_t(int C, int N, int n_spectra, SpecLayout lay, const void *src, void *dst, hipStream_t s) {
     constexpr int TB = kRowBytes / (int)sizeof(T);
     const int n_tb = (n_spectra + TB - 1) / TB;
-    const int64_t total = (int64_t)C * n_tb * N * 2 * TB;
-    hipLaunchKernelGGL(ingest_kernel<T>, dim3(grid_for(total)), dim3(kThreads), 0, s, static_cast<const T *>(src),
-                       static_cast<T *>(spec), C, N, n_spectra, n_tb, lay);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t export_t(int C, int N, int n_spectra, SpecLayout lay, const void *spec, void *dst, hipStream_t s) {
-    const int64_t total = (int64_t)n_spectra * C * N * 2;
-    hipLaunchKernelGGL(export_kernel<T>, dim3(grid_for(total)), dim3(kThreads), 0, s,
-                       static_cast<const T *>(spec), static_cast<T *>(dst), C, N, n_spectra, lay);
+    const int n_cc = (2 * N + kCols - 1) / kCols;
+    const int64_t grid = (int64_t)C * n_tb * n_cc;
+    if (grid < 1) return hipSuccess;
+    if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const void *pub = INGEST ? src : dst;
+    const bool vec = (2 * N * (int)sizeof(T)) % 16 == 0 && reinterpret_cast<uintptr_t>(pub) % 16 == 0;
+    const uint8_t *in = static_cast<const uint8_t *>(src);
+    uint8_t *out = static_cast<uint8_t *>(dst);
+    if (vec)
+        hipLaunchKernelGGL((relayout_kernel<T, INGEST, true>), dim3((unsigned)grid), dim3(kThreads), 0, s, in, out,
+                           C, N, n_spectra, n_tb, n_cc, lay);
+    else
+        hipLaunchKernelGGL((relayout_kernel<T, INGEST, false>), dim3((unsigned)grid), dim3(kThreads), 0, s, in, out,
+                           C, N, n_spectra, n_tb, n_cc, lay);
     return hipGetLastError();
 }
 
@@ -157,18 +210,18 @@ hipError_t export_t(int C, int N, int n_spectra, SpecLayout lay, const void *spe
 hipError_t launch_ingest(int prec, int C, int N, int n_spectra, SpecLayout lay, const void *src, void *spec,
                          hipStream_t stream) {
     switch (elem_bytes(prec)) {
-    case 4: return ingest_t<uint32_t>(C, N, n_spectra, lay, src, spec, stream);
-    case 2: return ingest_t<uint16_t>(C, N, n_spectra, lay, src, spec, stream);
-    default: return ingest_t<uint8_t>(C, N, n_spectra, lay, src, spec, stream);
+    case 4: return relayout_t<uint32_t, true>(C, N, n_spectra, lay, src, spec, stream);
+    case 2: return relayout_t<uint16_t, true>(C, N, n_spectra, lay, src, spec, stream);
+    default: return relayout_t<uint8_t, true>(C, N, n_spectra, lay, src, spec, stream);
     }
 }
 
 hipError_t launch_export(int prec, int C, int N, int n_spectra, SpecLayout lay, const void *spec, void *dst,
                          hipStream_t stream) {
     switch (elem_bytes(prec)) {
-    case 4: return export_t<uint32_t>(C, N, n_spectra, lay, spec, dst, stream);
-    case 2: return export_t<uint16_t>(C, N, n_spectra, lay, spec, dst, stream);
-    default: return export_t<uint8_t>(C, N, n_spectra, lay, spec, dst, stream);
+    case 4: return relayout_t<uint32_t, false>(C, N, n_spectra, lay, spec, dst, stream);
+    case 2: return relayout_t<uint16_t, false>(C, N, n_spectra, lay, spec, dst, stream);
+    default: return relayout_t<uint8_t, false>(C, N, n_spectra, lay, spec, dst, stream);
     }
 }
 
