@@ -115,9 +115,12 @@ CORR_API int64_t corr_spectra_bytes(const corr_params *params, int32_t n_spectra
 /*
  * Plan and allocate a correlator for the given shape.  Validates params
  * (CORR_E_INVALID_ARG / CORR_E_UNSUPPORTED), sizes the spectra buffer
- * (n_integrate spectra), the accumulators (C * N(N+1)/2 complex) and the
- * twiddle table, and fails with CORR_E_NOMEM when they exceed device_mem_cap
- * (or the device's free memory when the cap is 0): the failure mode of a GPU
+ * (n_integrate spectra), the accumulators (C * N(N+1)/2 complex), the
+ * twiddle tables and, from 2048 channels on, an F-engine scratch buffer
+ * (C * 128 * N * ceil(n_integrate / time block) bytes, or 1 GiB rounded down
+ * to whole C * 128-byte units if that is less).  It fails with CORR_E_NOMEM
+ * when these exceed device_mem_cap (or the device's free memory when the cap
+ * is 0): the failure mode of a GPU
  * that cannot hold all baselines of one FFT length (Section 3).  For
  * CORR_INT8, n_integrate above CORR_INT8_MAX_INTEGRATE is CORR_E_OVERFLOW.
  * hip_stream is a hipStream_t (NULL = the null stream); all later work of the

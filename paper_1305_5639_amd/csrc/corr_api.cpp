@@ -36,6 +36,8 @@ struct corr_ctx {
     float2 *twiddle = nullptr;
     float2 *twiddle2n = nullptr;       // exp(-j pi k / C), k < C (real-input F-engine)
     float *unit_scale = nullptr;       // C ones: the F-engine's scale when the caller gives none
+    void *gscr = nullptr;             // F-engine chunk scratch (kGatherMinC channels and up)
+    int64_t gscr_bytes = 0;
     float *scale2 = nullptr;          // s_k^2 of the F-engine's spectra
     float *scale2_user = nullptr;     // s_k^2 of caller spectra
     void *dump_tmp = nullptr;         // staging for converted dumps to host
@@ -243,7 +245,8 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
     const size_t acc_bytes = (size_t)C * B * 8;
     const size_t small_bytes = (size_t)C * 8 + 2 * (size_t)C * 4;
     const size_t dump_bytes = default_dump(params) ? 0 : (size_t)corr_visibility_bytes(params);
-    const size_t need = spec_bytes + acc_bytes + small_bytes + dump_bytes;
+    const size_t gscr_bytes = (size_t)gather_scratch_bytes(C, N, n_tb_cap);
+    const size_t need = spec_bytes + acc_bytes + small_bytes + dump_bytes + gscr_bytes;
     if (params->device_mem_cap && need > params->device_mem_cap) {
         char b[160];
         snprintf(b, sizeof b, "plan needs %zu bytes, cap is %llu", need,
@@ -296,6 +299,9 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
         return cleanup_fail(e == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP, "hipMalloc spectra failed");
     if ((e = hipMalloc(&h->acc, acc_bytes)) != hipSuccess)
         return cleanup_fail(e == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP, "hipMalloc accumulators failed");
+    if (gscr_bytes && (e = hipMalloc(&h->gscr, gscr_bytes)) != hipSuccess)
+        return cleanup_fail(e == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP, "hipMalloc F-engine scratch failed");
+    h->gscr_bytes = (int64_t)gscr_bytes;
     if ((e = hipMalloc(&h->twiddle, (size_t)C * sizeof(float2))) != hipSuccess ||
         (e = hipMalloc(&h->twiddle2n, (size_t)C * sizeof(float2))) != hipSuccess ||
         (e = hipMalloc(&h->unit_scale, (size_t)C * sizeof(float))) != hipSuccess ||
@@ -331,6 +337,7 @@ static void destroy_ctx(corr_ctx *h) {
     (void)hipFree(h->twiddle);
     (void)hipFree(h->twiddle2n);
     (void)hipFree(h->unit_scale);
+    (void)hipFree(h->gscr);
     (void)hipFree(h->scale2);
     (void)hipFree(h->scale2_user);
     (void)hipFree(h->dump_tmp);
@@ -381,7 +388,7 @@ corr_status corr_fengine_at(corr_handle h, const void *d_volts, int64_t ld_sampl
     if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
     e = launch_fengine(h->prec, h->C, h->N, static_cast<const float2 *>(d_volts), ld_samples, n_spectra,
                        d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->spec, h->lay,
-                       first_spectrum / time_block(h->prec), h->stream);
+                       FScratch{h->gscr, h->gscr_bytes}, first_spectrum / time_block(h->prec), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine launch");
     h->n_held = first_spectrum + n_spectra;
     h->held_from_fengine = true;
@@ -412,7 +419,7 @@ corr_status corr_fengine_real8_at(corr_handle h, const int8_t *d_samples, int64_
     if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
     e = launch_fengine_real8(h->prec, h->C, h->N, d_samples, ld_samples, n_spectra,
                              d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->twiddle2n, h->spec,
-                             h->lay, first_spectrum / time_block(h->prec), h->stream);
+                             h->lay, FScratch{h->gscr, h->gscr_bytes}, first_spectrum / time_block(h->prec), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "fengine_real8 launch");
     h->n_held = first_spectrum + n_spectra;
     h->held_from_fengine = true;
@@ -702,6 +709,7 @@ corr_status corr_create_batched(const corr_params *params, int32_t n, void *hip_
         const int TB = time_block(params[i].precision);
         need += (uint64_t)spec_buffer_bytes(params[i].n_channels, (int)N, (params[i].n_integrate + TB - 1) / TB,
                                             elem_bytes(params[i].precision)) +
+                (uint64_t)gather_scratch_bytes(params[i].n_channels, (int)N, (params[i].n_integrate + TB - 1) / TB) +
                 (uint64_t)params[i].n_channels * (N * (N + 1) / 2) * 8;
     }
     if (params[0].device_mem_cap && need > params[0].device_mem_cap)

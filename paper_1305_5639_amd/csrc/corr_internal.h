@@ -61,6 +61,28 @@ inline int64_t spec_buffer_bytes(int C, int N, int n_tb_cap, int elem) {
 }
 
 inline int elem_bytes(int prec) { return prec == P_FP32 ? 4 : (prec == P_FP16 ? 2 : 1); }
+
+// From kGatherMinC channels on, an F-engine workgroup holds too few spectra
+// to write useful pieces of the 64-byte rows (4 bytes of each at 2048
+// channels), and those scattered stores cap the kernel at 1-2.5 TB/s.  There
+// the F-engine runs in chunks: each chunk's spectra go to a scratch buffer in
+// the workgroups' natural order, contiguous per workgroup, and a gather
+// kernel moves them into the rows.  Scratch bytes per (input, time block):
+// C * 128.  kGatherScratchCap bounds the per-handle buffer (smaller chunks
+// measured slower: each chunk adds two kernel tails, and even 32 MB chunks
+// were not read back from the memory-side cache any faster).
+constexpr int kGatherMinC = 2048;
+constexpr int64_t kGatherScratchCap = (int64_t)1 << 30;
+struct FScratch {
+    void *buf;                        // device, library-owned; null below kGatherMinC
+    int64_t bytes;
+};
+inline int64_t gather_scratch_bytes(int C, int N, int n_tb_cap) {
+    if (C < kGatherMinC) return 0;
+    const int64_t unit = (int64_t)C * 2 * kRowBytes;
+    const int64_t all = unit * N * n_tb_cap;
+    return all < kGatherScratchCap ? all : (kGatherScratchCap / unit) * unit;
+}
 // Spectra per time block.
 inline int time_block(int prec) { return kRowBytes / elem_bytes(prec); }
 
@@ -70,16 +92,18 @@ inline int time_block(int prec) { return kRowBytes / elem_bytes(prec); }
 // time-blocked planar spectra buffer.  Spectra in [n_spectra, n_tb*TB) of the
 // last block are written as zeros.  inv_scale: C floats, never null.  The
 // spectra land from time block first_tb of the buffer on.
+// From kGatherMinC channels on the call runs in chunks through scr (see
+// FScratch), one F-engine and one gather launch per chunk.
 hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld,
                           int n_spectra, const float *inv_scale, const float2 *twiddle,
-                          void *spec, SpecLayout lay, int first_tb, hipStream_t stream);
+                          void *spec, SpecLayout lay, FScratch scr, int first_tb, hipStream_t stream);
 
 // F-engine on int8 real samples (Section 5): block a of row p is the 2C bytes
 // samples[p*ld + a*2C ..]; channels k < C of its length-2C DFT.  twiddle2n[k]
 // = exp(-j pi k / C), k < C.  ld even.
 hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, int64_t ld, int n_spectra,
                                 const float *inv_scale, const float2 *twiddle, const float2 *twiddle2n,
-                                void *spec, SpecLayout lay, int first_tb, hipStream_t stream);
+                                void *spec, SpecLayout lay, FScratch scr, int first_tb, hipStream_t stream);
 
 // X-engine: accumulate Eq. 2 over the first n_spectra spectra of the spectra
 // buffer into acc (spectra past n_spectra in the last time block are masked to

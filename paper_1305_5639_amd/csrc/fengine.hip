@@ -32,6 +32,8 @@
 // pass (one more LDS round trip for the partner value Z[C - k]).
 #include "corr_internal.h"
 
+#include <algorithm>
+
 namespace corr {
 namespace {
 
@@ -536,6 +538,10 @@ __global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_w
     //    faster without the test.
     constexpr bool NT = !REAL && (PREC == P_INT8 || PREC == P_FP8);
     constexpr bool SCALE_TEST = !REAL && (PREC == P_FP32 || PREC == P_FP16);
+    // GATHER: stores go to the chunk scratch (passed as spec) in natural
+    // order, [workgroup][plane][channel][spectrum], contiguous per workgroup.
+    constexpr bool GATHER = C >= kGatherMinC;
+    static_assert(!GATHER || T <= TB, "a gathered workgroup must lie within one time block");
     constexpr int LF = SPLIT ? 1 : 2;                  // floats per LDS element
     constexpr int NPL = 2 * C * S <= T * CP * 4 * LF ? 2 : 1;   // planes staged at a time
     static_assert(NPL * C * S <= T * CP * 4 * LF, "staging must fit the FFT buffer");
@@ -602,36 +608,113 @@ __global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_w
             const int a = a0 + x * (CH / ES);
             if (a >= n_valid_pad) continue;
             const int tb = tb0 + a / TB, within = a % TB;
-            uint8_t *dst = spec + (int64_t)tb * t_stride + (int64_t)k * k_stride + (int64_t)p * (2 * kRowBytes) +
-                           pl * kRowBytes + within * ES;
+            uint8_t *dst = GATHER ? spec + (int64_t)w * (2 * C * S) + (int64_t)pl0 * C * S + (int64_t)c * CH
+                                  : spec + (int64_t)tb * t_stride + (int64_t)k * k_stride +
+                                        (int64_t)p * (2 * kRowBytes) + pl * kRowBytes + within * ES;
             *reinterpret_cast<V *>(dst) = *reinterpret_cast<const V *>(stage + c * CH);
         }
     }
 }
 
+// Second step of a gathered F-engine chunk: the scratch holds, for chunk time
+// block tbl, chunk input i and piece g < GPT = 64 / S, workgroup w = (tbl np
+// + i) GPT + g's [plane][channel][S-byte piece] (piece g = spectra g T ..
+// g T + T - 1 of the block).  Each thread assembles one 16-byte quarter of a
+// 64-byte row (k, tb, p, plane) from 16 / S pieces; four neighbouring lanes
+// write one whole row.
+template <int S>
+__global__ __launch_bounds__(256) void fgather_kernel(const uint8_t *__restrict__ scr, uint8_t *__restrict__ spec,
+                                                      int log2c, int np, int ntb, int64_t ks, int64_t ts,
+                                                      int tb_first, int p0) {
+    static_assert(S == 1 || S == 2 || S == 4 || S == 8 || S == 16, "piece size");
+    constexpr int GPT = kRowBytes / S, PV = 16 / S;
+    const int C = 1 << log2c;
+    const int64_t wg_bytes = (int64_t)2 * C * S;
+    const int64_t total = (int64_t)ntb * np * 2 * C * 4;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int v = (int)(e & 3);
+        const int64_t r = e >> 2;
+        const int row = (int)(r & (2 * C - 1));        // plane * C + k
+        const int64_t r2 = r >> (log2c + 1);
+        const int i = (int)(r2 % np), tbl = (int)(r2 / np);
+        const uint8_t *src = scr + ((int64_t)(tbl * np + i) * GPT + v * PV) * wg_bytes + (int64_t)row * S;
+        uint4 out;
+        if constexpr (S == 16) {
+            out = *reinterpret_cast<const uint4 *>(src);
+        } else {
+            using W = typename Bytes<S>::T;
+            W piece[PV];
+#pragma unroll
+            for (int u = 0; u < PV; ++u) piece[u] = *reinterpret_cast<const W *>(src + u * wg_bytes);
+            __builtin_memcpy(&out, piece, 16);
+        }
+        uint8_t *dst = spec + (int64_t)(tb_first + tbl) * ts + (int64_t)(row & (C - 1)) * ks +
+                       (int64_t)(p0 + i) * (2 * kRowBytes) + (row >> log2c) * kRowBytes + v * 16;
+        *reinterpret_cast<uint4 *>(dst) = out;
+    }
+}
+
 template <int PREC, int C, bool REAL>
 hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                    const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, int tb0, hipStream_t stream) {
+                    const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, FScratch scr, int tb0,
+                    hipStream_t stream) {
     constexpr int TH = threads<C, PREC, REAL>();
     constexpr int T = TH * per_thread<C, PREC, REAL>() / C;
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
-    const int n_valid_pad = n_tb * TB;
-    const int groups = (n_valid_pad + T - 1) / T;
-    const int64_t n_work = (int64_t)N * groups;
-    if (n_work <= 0 || n_work > (int64_t)1 << 30) return hipErrorInvalidValue;
-    const int grid = (int)((n_work + 7) / 8) * 8;
-    hipLaunchKernelGGL((fengine_kernel<C, PREC, REAL>), dim3(grid), dim3(TH), 0, stream, in, ld, N,
-                       n_spectra, n_valid_pad, (int)n_work, inv_scale, tw, tw2,
-                       static_cast<uint8_t *>(spec), lay.ks, lay.ts, tb0);
-    return hipGetLastError();
+    auto run = [&](const void *src, int n_in, int ns, uint8_t *dst, int first_tb) -> hipError_t {
+        const int n_valid_pad = (ns + TB - 1) / TB * TB;
+        const int groups = (n_valid_pad + T - 1) / T;
+        const int64_t n_work = (int64_t)n_in * groups;
+        if (n_work <= 0 || n_work > (int64_t)1 << 30) return hipErrorInvalidValue;
+        const int grid = (int)((n_work + 7) / 8) * 8;
+        hipLaunchKernelGGL((fengine_kernel<C, PREC, REAL>), dim3(grid), dim3(TH), 0, stream, src, ld, n_in, ns,
+                           n_valid_pad, (int)n_work, inv_scale, tw, tw2, dst, lay.ks, lay.ts, first_tb);
+        return hipGetLastError();
+    };
+    if constexpr (C < kGatherMinC) {
+        return run(in, N, n_spectra, static_cast<uint8_t *>(spec), tb0);
+    } else {
+        // Chunks of whole time blocks of all inputs, or of one time block of
+        // a range of inputs, each filling at most the scratch.
+        constexpr int S = T * (int)sizeof(typename Elem<PREC>::T);
+        const int64_t unit = (int64_t)C * 2 * kRowBytes;
+        if (!scr.buf || scr.bytes < unit) return hipErrorInvalidValue;
+        const int np = (int)std::min<int64_t>(N, scr.bytes / unit);
+        const int ntb = np == N ? (int)std::min<int64_t>(n_tb, scr.bytes / (unit * N)) : 1;
+        int log2c = 0;
+        while ((1 << log2c) < C) ++log2c;
+        uint8_t *sb = static_cast<uint8_t *>(scr.buf);
+        for (int tbc = 0; tbc < n_tb; tbc += ntb) {
+            const int s0 = tbc * TB;
+            const int ns = std::min(ntb * TB, n_spectra - s0);
+            const int ntb_c = (ns + TB - 1) / TB;
+            for (int p0 = 0; p0 < N; p0 += np) {
+                const int npc = std::min(np, N - p0);
+                const void *src = REAL ? static_cast<const void *>(static_cast<const int8_t *>(in) + p0 * ld +
+                                                                   (int64_t)s0 * 2 * C)
+                                       : static_cast<const void *>(static_cast<const float2 *>(in) + p0 * ld +
+                                                                   (int64_t)s0 * C);
+                hipError_t e = run(src, npc, ns, sb, 0);
+                if (e != hipSuccess) return e;
+                const int64_t total = (int64_t)ntb_c * npc * 2 * C * 4;
+                const int64_t blocks = std::min<int64_t>((total + 255) / 256, (int64_t)1 << 20);
+                hipLaunchKernelGGL(fgather_kernel<S>, dim3((unsigned)blocks), dim3(256), 0, stream, sb,
+                                   static_cast<uint8_t *>(spec), log2c, npc, ntb_c, lay.ks, lay.ts, tb0 + tbc, p0);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+        }
+        return hipSuccess;
+    }
 }
 
 template <int PREC, bool REAL>
 hipError_t launch_p(int C, int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                    const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, int tb0, hipStream_t stream) {
+                    const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, FScratch scr, int tb0,
+                    hipStream_t stream) {
 #define CORR_FENGINE_CASE(c)                                                                            \
-    case c: return launch_c<PREC, c, REAL>(N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
+    case c: return launch_c<PREC, c, REAL>(N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, scr, tb0, stream);
     switch (C) {
         CORR_FENGINE_CASE(16)
         CORR_FENGINE_CASE(32)
@@ -650,12 +733,13 @@ hipError_t launch_p(int C, int N, const void *in, int64_t ld, int n_spectra, con
 
 template <bool REAL>
 hipError_t launch_any(int prec, int C, int N, const void *in, int64_t ld, int n_spectra, const float *inv_scale,
-                      const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, int tb0, hipStream_t stream) {
+                      const float2 *tw, const float2 *tw2, void *spec, SpecLayout lay, FScratch scr, int tb0,
+                      hipStream_t stream) {
     switch (prec) {
-    case P_FP32: return launch_p<P_FP32, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
-    case P_FP16: return launch_p<P_FP16, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
-    case P_FP8: return launch_p<P_FP8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
-    case P_INT8: return launch_p<P_INT8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, tb0, stream);
+    case P_FP32: return launch_p<P_FP32, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, scr, tb0, stream);
+    case P_FP16: return launch_p<P_FP16, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, scr, tb0, stream);
+    case P_FP8: return launch_p<P_FP8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, scr, tb0, stream);
+    case P_INT8: return launch_p<P_INT8, REAL>(C, N, in, ld, n_spectra, inv_scale, tw, tw2, spec, lay, scr, tb0, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -663,17 +747,17 @@ hipError_t launch_any(int prec, int C, int N, const void *in, int64_t ld, int n_
 }  // namespace
 
 hipError_t launch_fengine(int prec, int C, int N, const float2 *volts, int64_t ld, int n_spectra,
-                          const float *inv_scale, const float2 *twiddle, void *spec, SpecLayout lay, int first_tb,
-                          hipStream_t stream) {
-    return launch_any<false>(prec, C, N, volts, ld, n_spectra, inv_scale, twiddle, nullptr, spec, lay, first_tb,
+                          const float *inv_scale, const float2 *twiddle, void *spec, SpecLayout lay, FScratch scr,
+                          int first_tb, hipStream_t stream) {
+    return launch_any<false>(prec, C, N, volts, ld, n_spectra, inv_scale, twiddle, nullptr, spec, lay, scr, first_tb,
                              stream);
 }
 
 hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, int64_t ld, int n_spectra,
                                 const float *inv_scale, const float2 *twiddle, const float2 *twiddle2n, void *spec,
-                                SpecLayout lay, int first_tb, hipStream_t stream) {
-    return launch_any<true>(prec, C, N, samples, ld, n_spectra, inv_scale, twiddle, twiddle2n, spec, lay, first_tb,
-                            stream);
+                                SpecLayout lay, FScratch scr, int first_tb, hipStream_t stream) {
+    return launch_any<true>(prec, C, N, samples, ld, n_spectra, inv_scale, twiddle, twiddle2n, spec, lay, scr,
+                            first_tb, stream);
 }
 
 }  // namespace corr

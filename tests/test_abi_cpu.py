@@ -108,6 +108,20 @@ def test_nomem_budget_is_exact():
     assert s == corr.CORR_E_NOMEM
 
 
+def test_nomem_budget_counts_fengine_scratch():
+    """From 2048 channels the budget also holds the F-engine's chunk scratch
+    (C x 128 bytes per input and time block, here all of them)."""
+    N, C, A = 4, 2048, 64                                   # FP32: 4 time blocks of 16
+    n_tb = (A + 15) // 16
+    spec = C * n_tb * (N * 2 * 64 + 256)                    # time-block-major, padded channel stride
+    acc = C * N * (N + 1) // 2 * 8
+    small = C * 8 + 2 * C * 4
+    scratch = C * 128 * N * n_tb
+    s, _ = _create_status(n_stations=N, n_pols=1, n_channels=C, n_integrate=A,
+                          device_mem_cap=spec + acc + small + scratch - 1)
+    assert s == corr.CORR_E_NOMEM
+
+
 def test_int8_limit_accepted():
     p = corr.make_params(1, 1, 16, corr.CORR_INT8_MAX_INTEGRATE, "int8", device_mem_cap=1000)
     h = ctypes.c_void_p()
