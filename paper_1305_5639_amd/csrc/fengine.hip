@@ -38,26 +38,25 @@ namespace corr {
 namespace {
 
 // Threads per workgroup: 256, or 512 for the int8 / FP8 complex forms at C =
-// 512, 1024 and 8192, where twice the spectra per workgroup (so half as many
-// partial output rows) measured 3-17% faster on 2^28 samples; at 256, 2048 and
-// 4096 channels they gained nothing or lost (4096: 34% slower).
+// 512 and 1024, where twice the spectra per workgroup (so half as many
+// partial output rows) measured 3-10% faster on 2^28 samples; at 256 channels
+// they gained nothing.  From 2048 channels the chunked store and gather
+// leave no partial rows to save.
 template <int C, int PREC, bool REAL>
 constexpr int threads() {
-    return (!REAL && (PREC == P_INT8 || PREC == P_FP8) && (C == 512 || C == 1024 || C == 8192)) ? 512 : 256;
+    return (!REAL && (PREC == P_INT8 || PREC == P_FP8) && (C == 512 || C == 1024)) ? 512 : 256;
 }
 
-// Complex values per thread: 32, or 64 where 32 leaves a workgroup so few
-// spectra (8192/C) that its output rows go out in 1- to 4-byte pieces and the
-// store addressing saturates.  64 values spill a little (about 100 bytes), so
-// they are used only where they measured faster on 2^28 samples: int8 / FP8
-// from C = 4096 (1.40 -> 1.16 ms at 4096, 2.76 -> 2.09 ms at 8192) and FP16
-// at C = 8192 (2.72 -> 2.23 ms); at C = 2048 they were a third slower.  A
+// Complex values per thread.  64 once paid at C >= 4096, where 32 left a
+// workgroup so few spectra that its held-row stores went out in 1- to
+// 4-byte pieces; with the chunked store and gather used from 2048 channels
+// on, 32 (no spills) is faster at every size (4096 channels x 1024 inputs x
+// 1024 FP8: 16.2 -> 14.5 ms; 8192 x 256 x 128 int8: 1.53 -> 1.15 ms).  A
 // workgroup of TH threads transforms T = TH PT / C spectra; the helpers below
 // recover PT as T C / TH.
 template <int C, int PREC, bool REAL>
 constexpr int per_thread() {
-    return (!REAL && (((PREC == P_INT8 || PREC == P_FP8) && C >= 4096) || (PREC == P_FP16 && C >= 8192))) ? 64
-                                                                                                          : 32;
+    return 32;
 }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
