@@ -23,7 +23,8 @@ Also reported on one JSON line:
   xengine_shapes -- X-engine alone at the larger array shapes (512 inputs x
                   2048 channels x 2048 spectra for int8 / FP16, 1024 inputs x
                   4096 channels x 1024 spectra for FP8 / FP32), against each
-                  type's MFMA peak;
+                  type's MFMA peak, and the caller-spectra ingest (public
+                  layout into the held rows) and export at those shapes;
   batched      -- 64 uneven sub-arrays: persistent batched X-engine vs
                   per-array launches, and the graph-replayed step;
   config_steps -- whole F + X steps of the 256 x 2-input / 2048-channel (int8,
@@ -254,15 +255,46 @@ def run_shapes(torch, corr, reps=3):
             S = S.to(corr.SPECTRA_DTYPE[corr.PRECISIONS[prec]])
         c = corr.Correlator(st, 2, C, A, prec)
         c.xengine(A, S)
-        del S
+        # caller spectra: the same first call, ingest (public layout -> held
+        # rows) included; the ingest is its excess over the held-spectra call
+        dst = c.new_visibilities()
+        ts = []
+        for _ in range(reps):
+            c.dump(dst, reset=True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            c.xengine(A, S)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        caller_ms = sum(ts) / len(ts)
+        nbytes = S.numel() * S.element_size()
+        del S, dst
         torch.cuda.empty_cache()
         dst, ms = time_x(torch, c, A, reps)
         del dst
+        out = c.spectra()                          # export: held rows -> public layout
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            corr.corr_copy_spectra(c.handle, out)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        del out
+        export_ms = sum(ts) / len(ts)
+        torch.cuda.empty_cache()
+        ingest_ms = caller_ms - ms
         cm = N * (N + 1) // 2 * C * A
         tc = cm / (ms * 1e-3) / 1e12
         res[f"{prec}/{name}"] = {"inputs": N, "channels": C, "spectra": A, "xengine_ms": ms,
-                                 "xengine_tcmacs": tc, "mfma_frac": 8 * tc / PEAK[prec]}
-        log(f"shape {name} {prec}: X {ms:.3f} ms, {tc:.1f} TCMAC/s, {100 * 8 * tc / PEAK[prec]:.1f}% of MFMA peak")
+                                 "xengine_tcmacs": tc, "mfma_frac": 8 * tc / PEAK[prec],
+                                 "spectra_bytes": nbytes, "caller_spectra_xengine_ms": caller_ms,
+                                 "ingest_ms": ingest_ms, "ingest_tbs": 2 * nbytes / (ingest_ms * 1e-3) / 1e12,
+                                 "export_ms": export_ms, "export_tbs": 2 * nbytes / (export_ms * 1e-3) / 1e12}
+        log(f"shape {name} {prec}: X {ms:.3f} ms, {tc:.1f} TCMAC/s, {100 * 8 * tc / PEAK[prec]:.1f}% of MFMA peak; "
+            f"{nbytes / 1e9:.2f} GB caller spectra in {ingest_ms:.2f} ms, out {export_ms:.2f} ms")
         c.close()
         torch.cuda.empty_cache()
     # Rectangle (cross-only) X-engine: inputs [512, 1024) against [0, 512),
