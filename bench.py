@@ -16,6 +16,9 @@ Also reported on one JSON line:
                   the correlator's stream, against the MFMA peak of its type;
   forms        -- the same step in the FP16, int8 and FP8 forms, with X-engine
                   speed-ups over FP32;
+  pipelined    -- the main step in the steady state of a streaming correlator:
+                  two handles on two streams take alternate integrations, so
+                  one's F-engine overlaps the other's X-engine;
   equal_accuracy -- the same int8-valued spectra through the FP32, FP16 and
                   int8 X-engines: every value is exact in all three element
                   types, so the int8 result is the exact sum and the float
@@ -74,6 +77,8 @@ def parse():
     ap.add_argument("--batched-steps", type=int, default=8,
                     help="graph replays per integration in the batched section")
     ap.add_argument("--cpu-channels", type=int, default=768)
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the two-stream steady-state measurement of the main step")
     ap.add_argument("--no-equal-accuracy", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the whole F + X steps of the 2048- and 4096-channel workloads")
@@ -178,6 +183,37 @@ def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
     wall = (time.perf_counter() - t0) / steps
     timing = {"fengine_ms": ftimer.stats(), "xengine_and_dump_ms": xtimer.stats()}
     return c, out, inv, wall, ftimer.mean_ms(), xtimer.mean_ms(), timing
+
+
+def run_pipelined(torch, corr, w, prec, volts, steps, warmup, ref):
+    """Steady state of a correlator fed integration after integration: two
+    handles on two streams take alternate integrations, so the F-engine of
+    one can run while the X-engine of the previous one does.  Each step is
+    the same full F + X + fused dump; every output must equal the
+    single-stream step's."""
+    A = w.n_integrate
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    hs = [corr.Correlator(w.n_stations, w.n_pols, w.n_channels, A, prec, stream=s) for s in streams]
+    outs = [h.new_visibilities() for h in hs]
+    torch.cuda.synchronize()
+
+    def step(i):
+        h = hs[i % 2]
+        h.fengine(volts, A)
+        h.xengine_dump(A, outs[i % 2])
+
+    for i in range(max(warmup, 2)):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    equal = all(bool(torch.equal(o, ref)) for o in outs)
+    for h in hs:
+        h.close()
+    return wall, equal
 
 
 def int8_valued(torch, shape, seed):
@@ -611,6 +647,13 @@ def main():
     results = {prec: (out.cpu().numpy(), s2_main)}
     c.close()
     log(f"{prec}: step {wall * 1e3:.3f} ms, F {f_ms:.3f} ms, X {x_ms:.3f} ms")
+    pipelined = None
+    if not args.no_pipelined and prec == "fp32":
+        wall_p, equal_p = run_pipelined(torch, corr, w, prec, volts, args.steps, args.warmup, out)
+        pipelined = {"ms_per_step": wall_p * 1e3, "step_tcmacs": cmacs / wall_p / 1e12,
+                     "speedup_vs_one_stream": wall / wall_p, "outputs_equal_one_stream": equal_p,
+                     "streams": 2, "handles": 2}
+        log(f"{prec} two streams: step {wall_p * 1e3:.3f} ms ({wall / wall_p:.3f}x), outputs equal: {equal_p}")
 
     x_flops = 8.0 * cmacs
     x_achieved = x_flops / (x_ms * 1e-3) / 1e12
@@ -695,6 +738,7 @@ def main():
         "timing": timing,
         "roofline": roofline,
         "forms": forms,
+        "pipelined": pipelined,
         "equal_accuracy": equal,
         "xengine_shapes": shapes,
         "batched": batched,
