@@ -199,29 +199,39 @@ def corr_destroy(h) -> None:
     _check(lib().corr_destroy(h), "corr_destroy", h)
 
 
+def _rows(x, ld_samples):
+    """(pointer, ld) of a [rows][samples] buffer.  A 2-D tensor whose rows are
+    contiguous but spaced further apart (a slice of a longer recording, say)
+    is passed as is, its row stride as ld unless ld_samples is given."""
+    if isinstance(x, torch.Tensor) and x.dim() == 2 and x.stride(-1) == 1 and not x.is_contiguous():
+        return x.data_ptr(), (x.stride(0) if ld_samples is None else ld_samples)
+    return _ptr(x), (x.shape[-1] if ld_samples is None else ld_samples)
+
+
 def corr_fengine(h, volts, n_spectra: int, inv_scale=None, ld_samples: int | None = None,
                  first_spectrum: int = 0) -> None:
-    if ld_samples is None:
-        ld_samples = volts.shape[-1]
+    """volts: complex64 [n_inputs][ld] voltages (device); rows may be a
+    column slice of a wider tensor (ld = its row stride)."""
+    ptr, ld_samples = _rows(volts, ld_samples)
     if first_spectrum:
-        _check(lib().corr_fengine_at(h, _ptr(volts), int(ld_samples), int(n_spectra), _ptr(inv_scale),
+        _check(lib().corr_fengine_at(h, ptr, int(ld_samples), int(n_spectra), _ptr(inv_scale),
                                      int(first_spectrum)), "corr_fengine_at", h)
     else:
-        _check(lib().corr_fengine(h, _ptr(volts), int(ld_samples), int(n_spectra), _ptr(inv_scale)),
+        _check(lib().corr_fengine(h, ptr, int(ld_samples), int(n_spectra), _ptr(inv_scale)),
                "corr_fengine", h)
 
 
 def corr_fengine_real8(h, samples, n_spectra: int, inv_scale=None, ld_samples: int | None = None,
                        first_spectrum: int = 0) -> None:
     """samples: int8 [n_inputs][ld] real samples (device); spectrum a of row p
-    is the length-2C DFT of samples [a*2C, (a+1)*2C), channels 0..C-1."""
-    if ld_samples is None:
-        ld_samples = samples.shape[-1]
+    is the length-2C DFT of samples [a*2C, (a+1)*2C), channels 0..C-1.  Rows
+    may be a column slice of a wider tensor (ld = its row stride)."""
+    ptr, ld_samples = _rows(samples, ld_samples)
     if first_spectrum:
-        _check(lib().corr_fengine_real8_at(h, _ptr(samples), int(ld_samples), int(n_spectra), _ptr(inv_scale),
+        _check(lib().corr_fengine_real8_at(h, ptr, int(ld_samples), int(n_spectra), _ptr(inv_scale),
                                            int(first_spectrum)), "corr_fengine_real8_at", h)
     else:
-        _check(lib().corr_fengine_real8(h, _ptr(samples), int(ld_samples), int(n_spectra), _ptr(inv_scale)),
+        _check(lib().corr_fengine_real8(h, ptr, int(ld_samples), int(n_spectra), _ptr(inv_scale)),
                "corr_fengine_real8", h)
 
 

@@ -187,3 +187,17 @@ def test_batched_rejects_on_cpu():
     assert L.corr_set_tile(None, 64) == corr.CORR_E_INVALID_ARG
     t = ctypes.c_int32()
     assert L.corr_autotune(None, 1, ctypes.byref(t)) == corr.CORR_E_INVALID_ARG
+
+
+def test_row_slices_pass_with_their_stride():
+    """A column slice of a wider [rows][samples] tensor goes to the F-engine
+    entry points as is: its own address and the parent's row stride."""
+    import torch
+    v = torch.zeros((3, 1000), dtype=torch.complex64)
+    ptr, ld = corr.corr._rows(v[:, 256:], None)
+    assert ptr == v.data_ptr() + 256 * 8 and ld == 1000
+    assert corr.corr._rows(v, None) == (v.data_ptr(), 1000)
+    assert corr.corr._rows(v[:, 256:], 2000)[1] == 2000
+    with pytest.raises(ValueError):
+        corr.corr._rows(v.t(), None)                     # columns are not contiguous
+

@@ -131,3 +131,48 @@ def test_chunked_real_input_sampled(prec):
         n_mis, n_bad = tie_mismatches(sp.numpy().astype(np.float64), q_ref, y_pair, eps + 1e-30)
         say(f"  mismatches {n_mis} of {q_ref.size}, unexplained {n_bad}")
         assert n_bad == 0
+
+
+def test_chunked_fengine_graph_replay():
+    """A chunked F-engine (several F and gather launches per call) and the
+    X-engine captured in one HIP graph right after a reset: every replay, with
+    eager work between, equals the eager integration bit for bit (int8)."""
+    N, C, A = 520, 2048, 128                     # two appended calls of one 136 MB time block each
+    say(f"chunked graph replay int8 N={N} C={C} A={A}")
+    w = synth.small("fg-g", N, 1, C, A, seed=96)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        v = synth.voltages(w, device=DEV)
+        inv = torch.from_numpy(synth.inv_scale(w, "int8")).to(DEV)
+        with corr.Correlator(N, 1, C, A, "int8", stream=stream) as c:
+            def run():
+                c.fengine(v, 64, inv)
+                c.fengine(v[:, 64 * C:], A - 64, inv, first_spectrum=64)
+                c.xengine(A)
+            run()
+            ref = c.dump(reset=True).cpu().numpy()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                run()
+            for rep in range(3):
+                g.replay()
+                stream.synchronize()
+                got = c.dump(reset=False).cpu().numpy()
+                assert np.array_equal(got, ref), rep
+                torch.zeros(1000, device=DEV).sum().item()
+
+
+def test_batched_with_chunked_subarrays_int8():
+    """Sub-arrays from 2048 channels up (chunked F-engines, each with its own
+    scratch) beside small ones in one batched X-engine launch."""
+    shapes = [(20, 2, 2048, 70), (8, 1, 64, 100), (6, 2, 4096, 65)]
+    say("batched int8 with chunked F-engines")
+    with corr.Batch(shapes, "int8") as b:
+        for r, (ns, npol, C, A) in enumerate(shapes):
+            w = synth.small(f"fg-b{r}", ns, npol, C, A, seed=110 + r)
+            b.subs[r].fengine(synth.voltages(w, device=DEV), A, torch.from_numpy(synth.inv_scale(w, "int8")).to(DEV))
+        b.xengine([A for (_, _, _, A) in shapes])
+        for r, sub in enumerate(b.subs):
+            got = sub.dump().cpu().numpy().astype(np.int64)
+            sp = sub.spectra().cpu().numpy()
+            assert np.array_equal(got, oracle.xengine_i8(spectra_akp_to_apk(sp))), r
