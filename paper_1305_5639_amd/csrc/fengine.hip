@@ -575,8 +575,9 @@ __global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_w
     // v[q RL + r] holds channel k = j + r C/RL of spectrum t for last-pass
     // butterfly q, (t, j) as mapping LMAP gives them.  NPL planes at a time
     // are requantised and staged in LDS as [plane][channel][spectrum], then
-    // stored as runs of consecutive spectra of each (channel, plane) row.
-    // Destination: spec[k][tb][p][plane][TB].
+    // stored as runs of consecutive spectra of each (channel, plane) row:
+    // the row (k, tb, p, plane) at spec + tb t_stride + k k_stride + p 128 +
+    // plane 64, or, for GATHER, the workgroup's staged block as it stands.
     constexpr int CR = C / RL;
     using V = typename Bytes<CH>::T;
     constexpr int CPR = S / CH;                        // chunks per staged row
