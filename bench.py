@@ -6,23 +6,26 @@ X-engine (Eq. 2 over the triangle of all input pairs, autos included), and the
 dump of the visibilities to a device buffer with reset, fused into the
 X-engine's epilogue (corr_xengine_dump).
 
-Default workload: 128 stations x 2 pols (256 inputs), 1024 channels, 1000
-spectra per integration, FP32 (complex64 Gaussian voltages plus three
-point-source tones).  The value is algorithmic complex multiply-accumulates
-(N(N+1)/2 * C * A per step) per second of the whole step.
+Default workload: 512 stations x 2 pols (1024 inputs), 4096 channels (one
+GPU's frequency share of a larger array), 1024 spectra per integration, FP32
+-- the paper's single-precision arithmetic -- on complex64 Gaussian voltages
+plus three point-source tones.  The value is algorithmic complex
+multiply-accumulates (N(N+1)/2 * C * A per step) per second of the whole step.
 
 Also reported on one JSON line:
   roofline     -- the dominant kernel (the X-engine), timed with HIP events on
                   the correlator's stream, against the MFMA peak of its type;
-  forms        -- the same step in the FP16, int8 and FP8 forms, with X-engine
-                  speed-ups over FP32;
+  forms        -- the same step in the FP8, FP16 and int8 forms, with X-engine
+                  speed-ups over FP32 (the FP8 form is this workload's own
+                  reduced-precision configuration);
   pipelined    -- the main step in the steady state of a streaming correlator:
                   two handles on two streams take alternate integrations, so
                   one's F-engine overlaps the other's X-engine;
   equal_accuracy -- the same int8-valued spectra through the FP32, FP16 and
-                  int8 X-engines: every value is exact in all three element
-                  types, so the int8 result is the exact sum and the float
-                  forms differ from it by accumulation rounding only;
+                  int8 X-engines at the 512-input x 2048-channel x 2048-spectra
+                  shape: every value is exact in all three element types, so
+                  the int8 result is the exact sum and the float forms differ
+                  from it by accumulation rounding only;
   xengine_shapes -- X-engine alone at the larger array shapes (512 inputs x
                   2048 channels x 2048 spectra for int8 / FP16, 1024 inputs x
                   4096 channels x 1024 spectra for FP8 / FP32), against each
@@ -30,13 +33,14 @@ Also reported on one JSON line:
                   layout into the held rows) and export at those shapes;
   batched      -- 64 uneven sub-arrays: persistent batched X-engine vs
                   per-array launches, and the graph-replayed step;
-  config_steps -- whole F + X steps of the 256 x 2-input / 2048-channel (int8,
-                  FP16) and 512 x 2-input / 4096-channel (FP8) workloads;
+  config_steps -- whole F + X steps of the 128 x 2-input / 1024-channel (FP32)
+                  and 256 x 2-input / 2048-channel (int8, FP16) workloads;
   paper_workload -- 8-bit real samples, transform length 256, 128 to 3072
                   streams (the paper's own tests), FP32 and int8;
   cpu_baseline -- the oracle (float64 direct DFT + triple-loop correlation)
                   timed on a bounded channel sample on the host cores, which
-                  also gives each form's error against float64.
+                  also gives each form's error against float64, per sampled
+                  channel.
 """
 from __future__ import annotations
 
@@ -65,10 +69,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mwa-128x2-c1024")
+    ap.add_argument("--workload", default="ska-512x2-c4096")
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--forms", default="fp16,int8,fp8",
+    ap.add_argument("--forms", default="fp8,fp16,int8",
                     help="other precisions to time on the same workload ('' for none)")
+    ap.add_argument("--equal-workload", default="int8-256x2-c2048",
+                    help="shape of the equal-accuracy comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-sub-array batched (persistent, graph-captured) section")
@@ -76,7 +82,8 @@ def parse():
                     help="F-engine time blocks appended per batched X-engine launch")
     ap.add_argument("--batched-steps", type=int, default=8,
                     help="graph replays per integration in the batched section")
-    ap.add_argument("--cpu-channels", type=int, default=768)
+    ap.add_argument("--cpu-channels", type=int, default=16,
+                    help="channels of the oracle's bounded sample (0, C/2, C-1 and the tone bins included)")
     ap.add_argument("--no-pipelined", action="store_true",
                     help="skip the two-stream steady-state measurement of the main step")
     ap.add_argument("--no-equal-accuracy", action="store_true")
@@ -88,7 +95,7 @@ def parse():
                     help="skip the X-engine timings at the 512- and 1024-input shapes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "xengine_fp32_mwa-128x2-c1024_traffic.txt"),
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "xengine_traffic.txt"),
                     help="rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the X-engine (HBM bytes per launch)")
     return ap.parse_args()
 
@@ -367,11 +374,11 @@ def run_shapes(torch, corr, reps=3):
 
 
 def run_config_steps(torch, corr, synth, reps=3):
-    """Whole F + X steps (dump fused) of the larger configured workloads:
-    256 x 2 inputs, 2048 channels, 2048 spectra in int8 and FP16; 512 x 2
-    inputs, 4096 channels, 1024 spectra in FP8.  Voltages drawn on the device."""
+    """Whole F + X steps (dump fused) of the other configured workloads:
+    128 x 2 inputs, 1024 channels, 1000 spectra in FP32; 256 x 2 inputs, 2048
+    channels, 2048 spectra in int8 and FP16.  Voltages drawn on the device."""
     res = {}
-    for name, precs in (("int8-256x2-c2048", ("int8", "fp16")), ("ska-512x2-c4096", ("fp8",))):
+    for name, precs in (("mwa-128x2-c1024", ("fp32",)), ("int8-256x2-c2048", ("int8", "fp16"))):
         w = synth.WORKLOADS[name]
         N, C, A = w.n_inputs, w.n_channels, w.n_integrate
         volts = synth.voltages(w, device="cuda")
@@ -465,13 +472,20 @@ def run_paper_workload(torch, corr, synth, reps=3):
                          "real samples, transform length 256); context, not a target", **res}
 
 
-def cpu_baseline(torch, oracle, synth, w, volts, results, n_chan):
-    """The oracle on a channel sample of the same integration; errors per form."""
-    C, N, A = w.n_channels, w.n_inputs, w.n_integrate
+def sample_channels(w, n_chan):
+    """The oracle's bounded channel sample: 0, C/2, C-1, the tone bins and
+    seeded others, n_chan in all."""
+    C = w.n_channels
     rng = np.random.default_rng(12345)
     base = {0, C // 2, C - 1, *[b for b in w.tone_bins if b < C]}
     others = [int(x) for x in rng.permutation(C) if int(x) not in base]
-    chans = sorted(base | set(others[: max(0, n_chan - len(base))]))
+    return sorted(base | set(others[: max(0, n_chan - len(base))]))
+
+
+def cpu_baseline(torch, oracle, synth, w, volts, results, chans):
+    """The oracle on a channel sample of the same integration; errors per form
+    (results hold each form's visibilities of the sampled channels)."""
+    C, N, A = w.n_channels, w.n_inputs, w.n_integrate
     log(f"cpu_baseline: copying voltages to the host, oracle on {len(chans)} channels")
     v = volts.cpu().numpy()
     t0 = time.perf_counter()
@@ -485,13 +499,16 @@ def cpu_baseline(torch, oracle, synth, w, volts, results, n_chan):
     d = np.real(V64[:, [i * (i + 1) // 2 + i for i in range(N)]])
     norm = np.sqrt(np.maximum(d[:, il] * d[:, jl], 1e-300))
     for prec, (vis, s2) in results.items():
-        g = vis[chans].astype(np.float64)
+        g = vis.astype(np.float64)
         g = g[..., 0] + 1j * g[..., 1]
         if s2 is not None:
             g = g * s2[chans][:, None]
         eF = np.linalg.norm(g - V64, axis=1) / np.linalg.norm(V64, axis=1)
         en = np.abs(g - V64) / norm
-        errors[prec] = {"max_rel_frobenius": float(eF.max()), "max_normalised": float(en.max())}
+        errors[prec] = {"max_rel_frobenius": float(eF.max()), "max_normalised": float(en.max()),
+                        "per_channel": {"channels": [int(k) for k in chans],
+                                        "rel_frobenius": [float(x) for x in eF],
+                                        "max_normalised": [float(x) for x in en.max(axis=1)]}}
     return {
         "value": cmacs / t / 1e12,
         "unit": "TCMAC/s",
@@ -644,7 +661,8 @@ def main():
     s2_main = None
     if prec == "int8":
         s2_main = 1.0 / synth.inv_scale(w, prec).astype(np.float64) ** 2
-    results = {prec: (out.cpu().numpy(), s2_main)}
+    chans = sample_channels(w, args.cpu_channels)
+    results = {prec: (out[chans].cpu().numpy(), s2_main)}
     c.close()
     log(f"{prec}: step {wall * 1e3:.3f} ms, F {f_ms:.3f} ms, X {x_ms:.3f} ms")
     pipelined = None
@@ -669,7 +687,7 @@ def main():
         s2 = None
         if fp == "int8":
             s2 = 1.0 / synth.inv_scale(w, fp).astype(np.float64) ** 2
-        results[fp] = (of.cpu().numpy(), s2)
+        results[fp] = (of[chans].cpu().numpy(), s2)
         cf.close()
         del of
         xt = cmacs / (x_ms_f * 1e-3) / 1e12
@@ -682,7 +700,7 @@ def main():
 
     equal = None
     if not args.no_equal_accuracy:
-        equal = run_equal_accuracy(torch, corr, w)
+        equal = run_equal_accuracy(torch, corr, synth.WORKLOADS[args.equal_workload])
         log("equal accuracy: X " + ", ".join(f"{p} {equal[p]['xengine_ms']:.3f} ms" for p in ("fp32", "fp16", "int8")))
     shapes = None
     if not args.no_shapes:
@@ -707,7 +725,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cpu, errors = cpu_baseline(torch, oracle, synth, w, volts, results, args.cpu_channels)
+        cpu, errors = cpu_baseline(torch, oracle, synth, w, volts, results, chans)
         for fp, e in errors.items():
             if fp != prec:
                 forms[fp]["error_vs_float64"] = e

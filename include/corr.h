@@ -84,8 +84,11 @@ typedef struct {
     int32_t n_stations;      /* >= 1                                                     */
     int32_t n_pols;          /* 1 or 2; input p = station*n_pols + pol                    */
     int32_t n_channels;      /* C = FFT length = channel count; power of two, 16..8192   */
-    int32_t n_integrate;     /* spectra held per F-engine call (capacity of the spectra
-                                buffer); also the largest n_spectra of one call          */
+    int32_t n_integrate;     /* A of Eq. 2 for one X-engine call: the spectra the handle
+                                holds (capacity of its spectra buffer), so the largest
+                                n_spectra of one F- or X-engine call.  An integration
+                                may span several X-engine calls (it ends at a dump with
+                                reset), so it can be longer than n_integrate.           */
     int32_t precision;       /* corr_precision                                           */
     int32_t layout;          /* corr_layout used by corr_dump_visibilities               */
     int32_t order;           /* corr_order used by corr_dump_visibilities                */
@@ -100,7 +103,9 @@ typedef struct {
 /* Largest int8 integration whose worst case, 2*127^2 per spectrum, fits int32. */
 #define CORR_INT8_MAX_INTEGRATE 66572
 
-/* Number of products N(N+1)/2 per channel, N = n_stations*n_pols; -1 on bad params. */
+/* Number of products per channel: the triangle of non-redundant input pairs,
+ * autos included (Section 4), N(N+1)/2 with N = n_stations*n_pols, each a
+ * C_ij of Eq. 2; -1 on bad params. */
 CORR_API int64_t corr_n_products(const corr_params *params);
 
 /* Bytes one corr_dump_visibilities writes: products in the chosen layout x
@@ -200,7 +205,10 @@ CORR_API corr_status corr_fengine_real8_at(corr_handle h, const int8_t *d_sample
  *                 [n_spectra][n_channels][n_inputs][2] of the precision's
  *                 element (float32, binary16, E4M3 byte or int8; re then im),
  *                 16-byte aligned, n_spectra <= n_integrate.  Caller spectra
- *                 overwrite the handle's spectra buffer.
+ *                 overwrite the handle's spectra buffer.  CORR_INT8 caller
+ *                 values are taken in [-127, 127]: -128 is read as -127 (the
+ *                 same symmetric clamp as the F-engine's requantiser, which
+ *                 keeps negation exact and the int32 bound below valid).
  *   d_inv_scale : with caller spectra of the FP16 / FP8 forms, the float32
  *                 per-channel inv_s[k] they were scaled with (NULL = 1.0);
  *                 must be NULL when d_spectra is NULL (the F-engine's scale
@@ -228,6 +236,8 @@ CORR_API corr_status corr_xengine_dump(corr_handle h, const void *d_spectra, int
                                        const float *d_inv_scale, void *d_dst);
 
 /*
+ * Dump (Eq. 2 integrated over the spectra since the last reset; Section 4's
+ * triangle of non-redundant pairs, or the full matrix on request).
  * Write the integrated visibilities to dst in the handle's layout and order:
  * complex64 per product for the float forms (scaled to voltage units),
  * (re, im) int32 per product for CORR_INT8 (raw integer sums, exact).
@@ -240,8 +250,10 @@ CORR_API corr_status corr_xengine_dump(corr_handle h, const void *d_spectra, int
 CORR_API corr_status corr_dump_visibilities(corr_handle h, void *dst, int32_t dst_on_device, int32_t reset);
 
 /*
- * Copy the spectra held by the handle (the last F-engine output, i.e. the
- * requantised values the X-engine consumes) to dst in the public spectra
+ * Copy the spectra held by the handle -- the S[k] of Eq. 1 for each input and
+ * spectrum after the requantise epilogue, i.e. exactly the values Eq. 2
+ * correlates (the paper packs them into 8-bit integers before correlation,
+ * Section 5) -- to dst in the public spectra
  * layout [n_spectra][n_channels][n_inputs][2] of the precision's element.
  * dst holds corr_spectra_bytes(params, n) bytes, n = spectra held.  With
  * dst_on_device = 0 the call synchronises the stream.  For checking and
@@ -262,7 +274,10 @@ CORR_API corr_status corr_copy_spectra(corr_handle h, void *dst, int32_t dst_on_
  * for a triangle use corr_xengine.  d_out: caller-owned device buffer of
  * C * ni * nj (re, im) pairs, float32 (int32 for CORR_INT8, unscaled), 8-byte
  * aligned, [C][ni][nj] row-major; accumulate = 0 writes it, 1 adds to it.  The
- * handle's accumulators and counters are not touched.  Errors:
+ * handle's accumulators and counters are not touched, so the library does not
+ * track a running total across accumulate = 1 calls: for CORR_INT8 the caller
+ * keeps the spectra summed into one d_out at or below CORR_INT8_MAX_INTEGRATE,
+ * or its int32 entries can wrap.  Errors:
  * CORR_E_INVALID_ARG (ranges, overlap, pointer, flag), CORR_E_STATE (no or
  * too few spectra held), CORR_E_OVERFLOW (int8 over 66572 spectra in one call).
  */

@@ -29,10 +29,21 @@ __device__ __forceinline__ int lds_elem(int t, int j) {
     return t * W + ((chunk ^ (tg * ES)) << 4) + (byte & 15);
 }
 
+// Byte-wise max(b, -127) of four int8 values: a byte equal to 0x80 (-128)
+// becomes 0x81 (-127), every other byte is unchanged.  x marks the -128 bytes
+// as zero bytes; the zero-byte test below is exact (no borrow between bytes).
+__device__ __forceinline__ uint32_t sat_int8x4(uint32_t v) {
+    const uint32_t x = v ^ 0x80808080u;
+    const uint32_t nz = ((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x;
+    return v | ((~nz & 0x80808080u) >> 7);
+}
+
 // INGEST: public src -> held dst (the tail of the last block zero-filled);
 // else held src -> public dst.  VEC: public rows 16-byte aligned (2N * ES a
-// multiple of 16, base aligned), so public segments move as vectors.
-template <typename T, bool INGEST, bool VEC>
+// multiple of 16, base aligned), so public segments move as vectors.  SAT8
+// (int8 ingest): -128 is read as -127, the symmetric range the X-engine's
+// exact negation and the int32 overflow bound assume.
+template <typename T, bool INGEST, bool VEC, bool SAT8 = false>
 __global__ __launch_bounds__(kThreads) void relayout_kernel(const uint8_t *__restrict__ src,
                                                              uint8_t *__restrict__ dst, int C, int N,
                                                              int n_spectra, int n_tb, int n_cc, SpecLayout lay) {
@@ -64,6 +75,12 @@ __global__ __launch_bounds__(kThreads) void relayout_kernel(const uint8_t *__res
                         e[u] = col0 + u < cols ? *reinterpret_cast<const T *>(src + pub_addr(t, col0 + u)) : T(0);
                     __builtin_memcpy(&v, e, 16);
                 }
+            }
+            if constexpr (SAT8) {
+                v.x = sat_int8x4(v.x);
+                v.y = sat_int8x4(v.y);
+                v.z = sat_int8x4(v.z);
+                v.w = sat_int8x4(v.w);
             }
             *reinterpret_cast<uint4 *>(lds + lds_elem<T>(t, c * VE)) = v;
         }
@@ -184,7 +201,7 @@ int grid_for(int64_t n) {
     return (int)g;
 }
 
-template <typename T, bool INGEST>
+template <typename T, bool INGEST, bool SAT8 = false>
 hipError_t relayout_t(int C, int N, int n_spectra, SpecLayout lay, const void *src, void *dst, hipStream_t s) {
     constexpr int TB = kRowBytes / (int)sizeof(T);
     const int n_tb = (n_spectra + TB - 1) / TB;
@@ -197,11 +214,11 @@ hipError_t relayout_t(int C, int N, int n_spectra, SpecLayout lay, const void *s
     const uint8_t *in = static_cast<const uint8_t *>(src);
     uint8_t *out = static_cast<uint8_t *>(dst);
     if (vec)
-        hipLaunchKernelGGL((relayout_kernel<T, INGEST, true>), dim3((unsigned)grid), dim3(kThreads), 0, s, in, out,
-                           C, N, n_spectra, n_tb, n_cc, lay);
+        hipLaunchKernelGGL((relayout_kernel<T, INGEST, true, SAT8>), dim3((unsigned)grid), dim3(kThreads), 0, s, in,
+                           out, C, N, n_spectra, n_tb, n_cc, lay);
     else
-        hipLaunchKernelGGL((relayout_kernel<T, INGEST, false>), dim3((unsigned)grid), dim3(kThreads), 0, s, in, out,
-                           C, N, n_spectra, n_tb, n_cc, lay);
+        hipLaunchKernelGGL((relayout_kernel<T, INGEST, false, SAT8>), dim3((unsigned)grid), dim3(kThreads), 0, s, in,
+                           out, C, N, n_spectra, n_tb, n_cc, lay);
     return hipGetLastError();
 }
 
@@ -212,7 +229,9 @@ hipError_t launch_ingest(int prec, int C, int N, int n_spectra, SpecLayout lay, 
     switch (elem_bytes(prec)) {
     case 4: return relayout_t<uint32_t, true>(C, N, n_spectra, lay, src, spec, stream);
     case 2: return relayout_t<uint16_t, true>(C, N, n_spectra, lay, src, spec, stream);
-    default: return relayout_t<uint8_t, true>(C, N, n_spectra, lay, src, spec, stream);
+    default:
+        if (prec == P_INT8) return relayout_t<uint8_t, true, true>(C, N, n_spectra, lay, src, spec, stream);
+        return relayout_t<uint8_t, true>(C, N, n_spectra, lay, src, spec, stream);
     }
 }
 

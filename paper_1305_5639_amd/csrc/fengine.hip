@@ -4,8 +4,7 @@
 // One workgroup of TH threads (256, or 512 for some int8 / FP8 sizes)
 // transforms T = TH PT / C consecutive spectra of
 // one input (64 KB of complex64 voltages, one contiguous coalesced run); every
-// thread holds PT = 32 complex values (64 for some low-precision complex forms
-// at C >= 4096).  The FFT is a Stockham autosort transform
+// thread holds PT = 32 complex values.  The FFT is a Stockham autosort transform
 // with radices up to 32 done in registers: one pass for C <= 32, two for
 // C <= 1024 (one LDS round trip), three above.  The first pass reads straight
 // from global memory; the others read and write LDS rows whose index is padded
@@ -15,7 +14,9 @@
 // are scaled by inv_s[k], rounded to the spectra element type and staged in
 // LDS as [plane][channel][spectrum], which turns the channel-major FFT output
 // into runs of consecutive spectra per (channel, input, plane) row of the
-// X-engine layout.
+// X-engine layout.  From kGatherMinC channels on, a workgroup's staged output
+// goes instead to a scratch buffer in workgroup order, and fgather_kernel
+// assembles the rows from those pieces.
 //
 // Twiddles between passes are float32 values of exp(-j 2 pi m / C) computed
 // in float64 on the host: log2(R) table reads per butterfly, the other powers

@@ -11,18 +11,21 @@
 // operand is formed in registers (sign flip for float forms, a byte-wise SWAR
 // negate for int8, exact because the int8 range is symmetric).
 //
-// Tiling.  A workgroup (256 threads, 4 waves) owns a 128x128 block (rows I,
-// columns J <= I) of one channel; each wave a 64x64 quarter as 2x2 MFMA
-// 32x32 blocks with separate real and imaginary accumulators.  On diagonal
-// blocks the wave above the diagonal idles and the diagonal waves skip their
-// upper 32x32 block.  The K loop walks time blocks: each stage copies the
-// rows' contiguous 16 KB slab (128 inputs x 2 planes x 64 bytes) for I and J
-// from global memory into padded LDS rows (144-byte stride, conflict-free
-// 16-byte fragment reads), double-buffered with one barrier per stage.
-// Every lane reads 32 bytes per (fragment, plane) per stage, which is one K
-// step for FP8 (32x32x64), two for int8 (32x32x32) and FP16 (32x32x16), and
-// eight for FP32 (32x32x2).  Because the same K assignment is used for both
-// operands, the spectrum-to-slot order inside a stage does not matter.
+// Tiling.  A workgroup owns a TILE x TILE block (rows I, columns J <= I) of
+// one channel's triangle, TILE = 64 or 128.  Its waves form a 2 x (TILE / 32)
+// grid: each wave owns TILE / 2 rows and one 32-column block, as 32x32 MFMA
+// blocks with separate real and imaginary accumulators (TILE = 128: 8 waves of
+// 64 x 32, 512 threads; TILE = 64: 4 waves of 32 x 32).  On diagonal blocks
+// the waves whose columns lie wholly right of their rows idle, and a wave
+// whose first 32 rows do skips that row block.  The K loop walks time blocks
+// through a two-slot LDS ring filled by direct global-to-LDS copies
+// (global_load_lds_dwordx4): each stage holds the TILE unpadded 128-byte rows
+// (both planes) of each operand, with each row's 16-byte chunks XOR-swizzled
+// so that 16 consecutive rows cover all 64 LDS banks.  Every lane reads 32
+// bytes per (row block, plane) per stage, which is one K step for FP8
+// (32x32x64), two for int8 (32x32x32) and FP16 (32x32x16), and eight for FP32
+// (32x32x2).  Because the same K assignment is used for both operands, the
+// spectrum-to-slot order inside a stage does not matter.
 //
 // Workgroups map XCD-major (each XCD takes a contiguous range of
 // (channel, block) items) so one channel's blocks share an L2.
@@ -373,17 +376,17 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
             for (int q = 0; q < EH; ++q) {
                 const int r = EH * hh + q;
                 const int i = I0 + wi * QS + f * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                bool in;
+                bool inside;
                 int o;
                 if constexpr (RECT) {
-                    in = i < om.r_end && j < om.c_end;
+                    inside = i < om.r_end && j < om.c_end;
                     o = (i - om.r0) * (om.c_end - om.c0) + (j - om.c0);
                 } else {
-                    in = i < N && j <= i;
+                    inside = i < N && j <= i;
                     o = i * (i + 1) / 2 + j;
                 }
-                ok |= (uint32_t)in << q;
-                idx[q] = in ? o : 0;
+                ok |= (uint32_t)inside << q;
+                idx[q] = inside ? o : 0;
             }
             T2 old[EH];
             if (!first_call) {

@@ -167,3 +167,53 @@ def test_batched_real_input_sub_arrays_int8_exact():
             y = oracle.fengine_real8(xs[i], C, A) * invs[i].astype(np.float64)[None, None, :]
             q = spectra_akp_to_apk(sp).astype(np.float64)
             assert max(np.max(np.abs(q[..., 0] - y.real)), np.max(np.abs(q[..., 1] - y.imag))) <= 0.5 + 1e-3, i
+
+
+def _seed5_picks():
+    """Four sub-arrays of the 64-sub-array seed-5 draw: the fewest inputs, the
+    most inputs and two seeded others."""
+    ws = synth.batched_workloads()
+    by_n = sorted(range(len(ws)), key=lambda r: (ws[r].n_inputs, r))
+    lo, hi = by_n[0], by_n[-1]
+    rest = [r for r in range(len(ws)) if r not in (lo, hi)]
+    picks = [lo, hi] + [int(x) for x in np.random.default_rng(55).choice(rest, size=2, replace=False)]
+    return [ws[r] for r in picks]
+
+
+@pytest.mark.timeout(600)
+def test_batched_fp16_seed5_subarrays_vs_oracle():
+    """The batched persistent X-engine in FP16 (FP32 accumulation) on four
+    sub-arrays of the seed-5 uneven draw at their full shapes, F-engine
+    included, against the oracle on sampled channels: the X-engine on the
+    identical FP16 spectra (Eq. 2 in float64), and the whole F + X chain
+    against the float64 DFT (Eq. 1) and Eq. 2."""
+    ws = _seed5_picks()
+    shapes = [(w.n_stations, w.n_pols, w.n_channels, w.n_integrate) for w in ws]
+    say(f"batched fp16 seed-5 sub-arrays {shapes}")
+    vs, invs = [], []
+    with corr.Batch(shapes, "fp16") as b:
+        for i, w in enumerate(ws):
+            vs.append(synth.voltages(w, device=DEV))
+            invs.append(synth.inv_scale(w, "fp16"))
+            b.subs[i].fengine(vs[i], w.n_integrate, torch.from_numpy(invs[i]).to(DEV))
+        b.xengine([w.n_integrate for w in ws])
+        for i, w in enumerate(ws):
+            N, C, A = w.n_inputs, w.n_channels, w.n_integrate
+            chans = sorted({0, C // 2, C - 1, *w.tone_bins,
+                            *[int(x) for x in np.random.default_rng(100 + i).choice(C, size=2, replace=False)]})
+            got = cplx(b.subs[i].dump()[chans].cpu().numpy())
+            sp = b.subs[i].spectra()                                   # [A][C][N][2] binary16
+            q = sp[:, chans].to(torch.float64).cpu().numpy()
+            del sp
+            s2 = 1.0 / invs[i][chans].astype(np.float64) ** 2
+            ref_q = oracle.xengine_f64(spectra_akp_to_apk(cplx(q))) * s2[:, None]
+            eF, en = vis_errors(got, ref_q, N)
+            say(f"  sub-array {i} ({N} inputs, {C} ch, {A} spectra) vs identical FP16 spectra: "
+                f"max e_F {eF.max():.2e}  max e_n {en.max():.2e}")
+            assert eF.max() < 1e-5 and en.max() < 1e-5, i
+            ref64 = oracle.xengine_f64(oracle.fengine(vs[i].cpu().numpy(), C, A, chans))
+            eF, en = vis_errors(got, ref64, N)
+            say(f"  sub-array {i} vs float64 F + X: max e_F {eF.max():.2e}  max e_n {en.max():.2e}")
+            assert en.max() < 1e-3, i
+            vs[i] = None
+            torch.cuda.empty_cache()

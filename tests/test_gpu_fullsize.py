@@ -70,12 +70,19 @@ def test_int8_full_size_bit_exact_and_fp16_error():
         c.xengine(A)
         vis = c.dump()
         sp = c.spectra()                                          # [A][C][N][2] int8
-        q = sp[:, chans].cpu().numpy()                            # [A][Cs][N][2]
+        sp_h = sp.cpu().numpy()                                   # every channel, 4.3 GB
         del sp
-    got = vis[chans].cpu().numpy().astype(np.int64)
-    say(f"  int64 oracle on the GPU's int8 spectra, channels {chans}")
-    ref = oracle.xengine_i8(np.ascontiguousarray(np.swapaxes(q, 1, 2)))
-    assert np.array_equal(got, ref)
+    q = sp_h[:, chans]                                            # [A][Cs][N][2]
+    vis_h = vis.cpu().numpy()                                     # [C][B][2] int32
+    got = vis_h[chans].astype(np.int64)
+    # Eq. 2 in exact integers on EVERY channel, in channel chunks (bounded host
+    # memory): the X-engine must equal the int64 oracle bit for bit.
+    step = 256
+    for c0 in range(0, C, step):
+        say(f"  int64 oracle on the GPU's int8 spectra, channels [{c0}, {c0 + step})")
+        ref = oracle.xengine_i8(np.ascontiguousarray(np.swapaxes(sp_h[:, c0:c0 + step], 1, 2)))
+        assert np.array_equal(vis_h[c0:c0 + step].astype(np.int64), ref), c0
+    del sp_h, vis_h
     # requantiser on the sample: codes equal the oracle's rounding of the
     # float64 DFT, up to rounding ties
     vh = v.cpu().numpy()
@@ -101,14 +108,19 @@ def test_int8_full_size_bit_exact_and_fp16_error():
 
 
 @pytest.mark.timeout(900)
-def test_ska_fp8_full_size():
+def test_ska_fp8_and_fp32_full_size():
+    """1024 inputs x 4096 channels x 1024 spectra: the FP8 form and the plain
+    FP32 path, each as a whole F + X step on complex64 voltages, against the
+    float64 oracle (Eq. 1 then Eq. 2) on sampled channels that include 0, C/2
+    and C - 1."""
     w = synth.WORKLOADS["ska-512x2-c4096"]
     N, C, A = w.n_inputs, w.n_channels, w.n_integrate
-    say(f"full size fp8 {w.name}")
+    say(f"full size fp8 + fp32 {w.name}")
     torch.cuda.empty_cache()
     v = synth.voltages(w, device=DEV)
     inv = synth.inv_scale(w, "fp8")
-    chans = _sample(w, 0, seed=2)[:4]
+    chans = _sample(w, 2, seed=2)
+    assert {0, C // 2, C - 1} <= set(chans)
     with corr.Correlator(w.n_stations, w.n_pols, C, A, "fp8") as c:
         c.fengine(v, A, torch.from_numpy(inv).to(DEV))
         c.xengine(A)
@@ -120,15 +132,42 @@ def test_ska_fp8_full_size():
         q8 = sp.view(torch.uint8)[:, chans].cpu()
         q = q8.view(torch.float8_e4m3fn).to(torch.float64).numpy()
         del sp
+    torch.cuda.empty_cache()
     assert autos_ok
     s2 = 1.0 / inv[chans].astype(np.float64) ** 2
     ref_q = oracle.xengine_f64(np.ascontiguousarray(np.swapaxes(cplx(q), 1, 2))) * s2[:, None]
     eF, en = vis_errors(got, ref_q, N)
     say(f"  vs identical FP8 spectra: max e_F {eF.max():.2e}  max e_n {en.max():.2e}")
     assert eF.max() < 1e-4 and en.max() < 1e-4
+
+    # the plain FP32 path on the same voltages
+    say("  fp32 F + X at full size")
+    with corr.Correlator(w.n_stations, w.n_pols, C, A, "fp32") as c:
+        c.fengine(v, A)
+        c.xengine(A)
+        vis = c.dump()
+        got32 = cplx(vis[chans].cpu().numpy())
+        autos = vis[:, torch.as_tensor(_autos_idx(N), device=DEV)]
+        autos_real = bool((autos[..., 1] == 0).all()) and bool((autos[..., 0] >= 0).all())
+        auto_sum = autos[..., 0].double().sum(dim=0).cpu().numpy()
+        del vis, autos
+    torch.cuda.empty_cache()
+    assert autos_real
+    # Parseval on every channel's autos: sum_k C_ii[k] = C sum_n |s_i[n]|^2
+    power = (v.real.double() ** 2 + v.imag.double() ** 2).sum(dim=1).cpu().numpy()
+    rel = np.abs(auto_sum - C * power) / (C * power)
+    say(f"  fp32 Parseval on autos: max rel {rel.max():.2e}")
+    assert rel.max() < 1e-5
+
     vh = v.cpu().numpy()
+    del v
+    torch.cuda.empty_cache()
     say(f"  float64 oracle DFT on channels {chans}")
     ref64 = oracle.xengine_f64(oracle.fengine(vh, C, A, chans))
+    del vh
+    eF, en = vis_errors(got32, ref64, N)
+    say(f"  fp32 vs float64: max e_F {eF.max():.2e}  max e_n {en.max():.2e}")
+    assert eF.max() < 1e-5 and en.max() < 1e-5
     eF, en = vis_errors(got, ref64, N)
     say(f"  fp8 vs float64 per channel e_F {np.array2string(eF, precision=2)}  max e_n {en.max():.2e}")
     assert en.max() < 0.1
