@@ -523,16 +523,27 @@ def cpu_baseline(torch, oracle, synth, w, volts, results, chans):
 
 
 def host_cpu():
-    """CPU model and logical CPU count of the host the oracle ran on."""
-    model = ""
+    """CPU model (name, family / model / stepping numbers, clock), logical CPU
+    count and the threads this process may use, of the host the oracle ran on."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+            if ":" not in line:
+                if info:
+                    break
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            if k in ("vendor_id", "model name", "cpu family", "model", "stepping", "cpu MHz") and k not in info:
+                info[k] = v
     except OSError:
         pass
-    return {"model": model, "logical_cpus": os.cpu_count()}
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return {"model": info.get("model name", ""), "vendor": info.get("vendor_id", ""),
+            "family_model_stepping": [info.get("cpu family"), info.get("model"), info.get("stepping")],
+            "mhz": info.get("cpu MHz"), "logical_cpus": os.cpu_count(), "usable_cpus": allowed}
 
 
 def run_batched(torch, corr, synth, steps_per_integration, blocks_per_x=4, reps=3):
