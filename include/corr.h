@@ -338,6 +338,40 @@ CORR_API corr_status corr_batch_get(corr_batch_handle b, int32_t i, corr_handle 
 CORR_API corr_status corr_xengine_batched(corr_batch_handle b, const int32_t *n_spectra);
 CORR_API corr_status corr_destroy_batched(corr_batch_handle b);
 
+/*
+ * X-engine on caller spectra with no allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The same result as a handle of
+ * these params (CORR_TRI_LOWER / CORR_CHAN_MAJOR only) doing
+ * corr_xengine(h, d_spectra, n_spectra, d_inv_scale) on zeroed accumulators
+ * (accumulate = 0) or on accumulators holding d_vis (accumulate = 1), then
+ * a dump to d_vis: no handle, nothing allocated or freed.  Staging lives in a
+ * 32 MiB device array of the library, one per device, that every call on the
+ * device shares: calls that overlap on one device (other streams or host
+ * threads) race and must be serialised by the caller.
+ *   params      : n_stations, n_pols, n_channels, precision, layout, order as
+ *                 for corr_create (n_integrate and device_mem_cap unused).
+ *   d_spectra   : [n_spectra][n_channels][n_inputs][2] public spectra, as
+ *                 for corr_xengine (int8: -128 is read as -127), 16-byte
+ *                 aligned.
+ *   d_inv_scale : FP16 / FP8: the float32 per-channel inv_s[k] (NULL = 1.0);
+ *                 NULL for FP32 and int8.
+ *   d_vis       : corr_visibility_bytes(params) bytes, 8-byte aligned;
+ *                 written (accumulate = 0) or added to (1), in the dump's
+ *                 units (int8: raw int32 sums; for int8 the caller keeps the
+ *                 total spectra summed into d_vis within
+ *                 CORR_INT8_MAX_INTEGRATE).
+ *   hip_stream  : the stream the work is enqueued on (asynchronous).
+ * Errors: as corr_create for params; CORR_E_INVALID_ARG (pointers, flags);
+ * CORR_E_OVERFLOW (int8 over 66572 spectra in one call); CORR_E_UNSUPPORTED
+ * when one channel's held spectra (n_inputs x ceil(n_spectra / time block) x
+ * 128 bytes, time block as for corr_fengine_at) do not fit the staging array
+ * next to the C scales -- about 32 MiB; CORR_E_HIP.
+ */
+CORR_API corr_status corr_xengine_noalloc(const corr_params *params, const void *d_spectra, int32_t n_spectra,
+                                          const float *d_inv_scale, void *d_vis, int32_t accumulate,
+                                          void *hip_stream);
+
 /* Static text of a status code. */
 CORR_API const char *corr_status_string(corr_status s);
 

@@ -44,7 +44,7 @@ ABI_FUNCTIONS = (
     "corr_copy_spectra", "corr_get_counts", "corr_status_string", "corr_last_error",
     "corr_set_tile", "corr_autotune", "corr_create_batched", "corr_batch_get",
     "corr_xengine_batched", "corr_destroy_batched", "corr_xengine_rect", "corr_fengine_real8",
-    "corr_fengine_at", "corr_fengine_real8_at", "corr_xengine_dump",
+    "corr_fengine_at", "corr_fengine_real8_at", "corr_xengine_dump", "corr_xengine_noalloc",
 )
 
 
@@ -109,9 +109,10 @@ def lib() -> ctypes.CDLL:
         L.corr_xengine_batched.argtypes = [P, ctypes.POINTER(i32)]
         L.corr_destroy_batched.argtypes = [P]
         L.corr_xengine_rect.argtypes = [P, i32, i32, i32, i32, i32, P, i32]
+        L.corr_xengine_noalloc.argtypes = [PP, P, i32, P, P, i32, P]
         for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_fengine_real8", "corr_fengine_at",
                   "corr_fengine_real8_at", "corr_xengine", "corr_xengine_dump",
-                  "corr_xengine_rect",
+                  "corr_xengine_rect", "corr_xengine_noalloc",
                   "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts", "corr_set_tile",
                   "corr_autotune", "corr_create_batched", "corr_batch_get", "corr_xengine_batched",
                   "corr_destroy_batched"):
@@ -247,6 +248,12 @@ def corr_xengine_dump(h, spectra, n_spectra: int, inv_scale, dst) -> None:
 def corr_xengine_rect(h, i0: int, ni: int, j0: int, nj: int, n_spectra: int, out, accumulate: bool = False) -> None:
     _check(lib().corr_xengine_rect(h, int(i0), int(ni), int(j0), int(nj), int(n_spectra), _ptr(out),
                                    int(bool(accumulate))), "corr_xengine_rect", h)
+
+
+def corr_xengine_noalloc(params: corr_params, spectra, n_spectra: int, inv_scale, vis, accumulate: bool = False,
+                         stream=None) -> None:
+    _check(lib().corr_xengine_noalloc(ctypes.byref(params), _ptr(spectra), int(n_spectra), _ptr(inv_scale),
+                                      _ptr(vis), int(bool(accumulate)), _stream(stream)), "corr_xengine_noalloc")
 
 
 def corr_dump_visibilities(h, dst, reset: bool = True, dst_on_device: int | None = None) -> None:

@@ -201,12 +201,16 @@ int grid_for(int64_t n) {
     return (int)g;
 }
 
+// nk: channels moved (the grid); C stays the channel stride of the public
+// layout, so a public pointer advanced by k0 channels moves channels
+// [k0, k0 + nk) to held channels [0, nk).
 template <typename T, bool INGEST, bool SAT8 = false>
-hipError_t relayout_t(int C, int N, int n_spectra, SpecLayout lay, const void *src, void *dst, hipStream_t s) {
+hipError_t relayout_t(int C, int N, int n_spectra, SpecLayout lay, const void *src, void *dst, hipStream_t s,
+                      int nk = -1) {
     constexpr int TB = kRowBytes / (int)sizeof(T);
     const int n_tb = (n_spectra + TB - 1) / TB;
     const int n_cc = (2 * N + kCols - 1) / kCols;
-    const int64_t grid = (int64_t)C * n_tb * n_cc;
+    const int64_t grid = (int64_t)(nk < 0 ? C : nk) * n_tb * n_cc;
     if (grid < 1) return hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     const void *pub = INGEST ? src : dst;
@@ -232,6 +236,19 @@ hipError_t launch_ingest(int prec, int C, int N, int n_spectra, SpecLayout lay, 
     default:
         if (prec == P_INT8) return relayout_t<uint8_t, true, true>(C, N, n_spectra, lay, src, spec, stream);
         return relayout_t<uint8_t, true>(C, N, n_spectra, lay, src, spec, stream);
+    }
+}
+
+hipError_t launch_ingest_channels(int prec, int C, int k0, int nk, int N, int n_spectra, SpecLayout lay,
+                                  const void *src, void *spec, hipStream_t stream) {
+    if (k0 < 0 || nk < 1 || k0 + nk > C) return hipErrorInvalidValue;
+    const uint8_t *s0 = static_cast<const uint8_t *>(src) + (int64_t)k0 * 2 * N * elem_bytes(prec);
+    switch (elem_bytes(prec)) {
+    case 4: return relayout_t<uint32_t, true>(C, N, n_spectra, lay, s0, spec, stream, nk);
+    case 2: return relayout_t<uint16_t, true>(C, N, n_spectra, lay, s0, spec, stream, nk);
+    default:
+        if (prec == P_INT8) return relayout_t<uint8_t, true, true>(C, N, n_spectra, lay, s0, spec, stream, nk);
+        return relayout_t<uint8_t, true>(C, N, n_spectra, lay, s0, spec, stream, nk);
     }
 }
 

@@ -860,3 +860,106 @@ corr_status corr_destroy_batched(corr_batch_handle b) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// X-engine without allocation.  The staging of caller spectra in the
+// X-engine's held-row layout (the handle's spectra buffer in corr_xengine)
+// is a file-scope device array instead, kNoAllocScratch bytes per device:
+// the per-channel scales s_k^2 first, then the held rows of as many
+// channels as fit, correlated chunk by chunk.  Every call on a device shares
+// its array; calls that overlap on one device race.
+namespace {
+
+constexpr int64_t kNoAllocScratch = (int64_t)32 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratch];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// The device address of `scratch` on the current device (taken once per
+// device); the array's name is only a host-side stand-in.
+hipError_t scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+corr_status corr_xengine_noalloc(const corr_params *params, const void *d_spectra, int32_t n_spectra,
+                                 const float *d_inv_scale, void *d_vis, int32_t accumulate, void *hip_stream) {
+    std::string msg;
+    corr_status s = check_params(params, msg);
+    if (s != CORR_OK) return fail(nullptr, s, msg);
+    if (!default_dump(params))
+        return fail(nullptr, CORR_E_UNSUPPORTED, "the no-alloc X-engine writes the lower-triangle, channel-major layout");
+    if (n_spectra < 1) return fail(nullptr, CORR_E_INVALID_ARG, "n_spectra must be >= 1");
+    if (!d_spectra || !aligned(d_spectra, 16))
+        return fail(nullptr, CORR_E_INVALID_ARG, "d_spectra must be a 16-byte aligned device pointer");
+    if (!d_vis || !aligned(d_vis, 8)) return fail(nullptr, CORR_E_INVALID_ARG, "d_vis must be an 8-byte aligned device pointer");
+    if (accumulate != 0 && accumulate != 1) return fail(nullptr, CORR_E_INVALID_ARG, "accumulate must be 0 or 1");
+    const int prec = params->precision;
+    if (d_inv_scale && (prec == P_FP32 || prec == P_INT8))
+        return fail(nullptr, CORR_E_INVALID_ARG, "d_inv_scale applies only to FP16/FP8 spectra");
+    if (d_inv_scale && !aligned(d_inv_scale, 4)) return fail(nullptr, CORR_E_INVALID_ARG, "d_inv_scale misaligned");
+    if (prec == P_INT8 && n_spectra > CORR_INT8_MAX_INTEGRATE)
+        return fail(nullptr, CORR_E_OVERFLOW, "int8 call over 66572 spectra could overflow int32");
+    const int N = (int)n_inputs(params), C = params->n_channels;
+    const int TB = time_block(prec);
+    const int n_tb = (n_spectra + TB - 1) / TB;
+    // scratch: s_k^2 (C floats, rounded up to 256 bytes), then channel-major
+    // held rows of nk channels
+    const int64_t s2_bytes = ((int64_t)C * 4 + 255) / 256 * 256;
+    const SpecLayout lay{(int64_t)n_tb * N * 2 * kRowBytes + kChannelPad, (int64_t)N * 2 * kRowBytes};
+    const int64_t nk64 = (kNoAllocScratch - s2_bytes) / lay.ks;
+    if (nk64 < 1) {
+        char b[200];
+        snprintf(b, sizeof b, "one channel of %d inputs x %d spectra needs %lld scratch bytes; the no-alloc "
+                 "scratch holds %lld", N, n_spectra, (long long)(s2_bytes + lay.ks), (long long)kNoAllocScratch);
+        return fail(nullptr, CORR_E_UNSUPPORTED, b);
+    }
+    const int nk = (int)std::min<int64_t>(nk64, C);
+
+    // ---- HIP from here on ----
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    void *base = nullptr;
+    hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+    float *s2 = static_cast<float *>(base);
+    uint8_t *spec = static_cast<uint8_t *>(base) + s2_bytes;
+    const bool scaled = prec == P_FP16 || prec == P_FP8;
+    if (scaled && (e = launch_scale2(C, d_inv_scale, s2, stream)) != hipSuccess)
+        return hip_fail(nullptr, e, "scale2 launch");
+    const int tile = (N <= 64 || prec == P_FP32) ? 64 : 128;
+    const int64_t B = (int64_t)N * (N + 1) / 2;
+    for (int k0 = 0; k0 < C; k0 += nk) {
+        const int n = std::min(nk, C - k0);
+        e = launch_ingest_channels(prec, C, k0, n, N, n_spectra, lay, d_spectra, spec, stream);
+        if (e != hipSuccess) return hip_fail(nullptr, e, "ingest launch");
+        uint8_t *vis = static_cast<uint8_t *>(d_vis) + (int64_t)k0 * B * 8;
+        e = launch_xengine(prec, tile, n, N, n_spectra, spec, lay, scaled ? s2 + k0 : nullptr, vis, vis,
+                           accumulate ? 0 : 1, stream);
+        if (e != hipSuccess) return hip_fail(nullptr, e, "xengine launch");
+    }
+    return CORR_OK;
+}
+
+}  // extern "C"

@@ -169,6 +169,10 @@ hipError_t launch_ingest(int prec, int C, int N, int n_spectra, SpecLayout lay, 
                          void *spec, hipStream_t stream);
 hipError_t launch_export(int prec, int C, int N, int n_spectra, SpecLayout lay, const void *spec,
                          void *dst, hipStream_t stream);
+// Ingest of channels [k0, k0 + nk) of public spectra with C channels into held
+// channels [0, nk) of spec (laid out by lay).
+hipError_t launch_ingest_channels(int prec, int C, int k0, int nk, int N, int n_spectra, SpecLayout lay,
+                                  const void *src, void *spec, hipStream_t stream);
 
 // Dump conversion from the lower-triangle channel-major accumulators into a
 // layout (0 lower, 1 upper, 2 full) and order (0 chan-major, 1 baseline-major).

@@ -201,3 +201,27 @@ def test_row_slices_pass_with_their_stride():
     with pytest.raises(ValueError):
         corr.corr._rows(v.t(), None)                     # columns are not contiguous
 
+
+
+def test_noalloc_rejects_on_cpu():
+    """The no-alloc X-engine decides every argument and size error before any
+    HIP call (fake device addresses are never touched)."""
+    L = corr.lib()
+    fake_s, fake_v = 1 << 20, 2 << 20                     # 16-byte aligned, never dereferenced
+    p = corr.make_params(8, 2, 64, 1, "int8")
+    call = lambda params, s=fake_s, n=64, inv=None, v=fake_v, acc=0: L.corr_xengine_noalloc(
+        ctypes.byref(params) if params is not None else None, s, n, inv, v, acc, None)
+    assert call(None) == corr.CORR_E_INVALID_ARG
+    assert call(p, s=None) == corr.CORR_E_INVALID_ARG
+    assert call(p, s=fake_s + 8) == corr.CORR_E_INVALID_ARG          # misaligned spectra
+    assert call(p, v=None) == corr.CORR_E_INVALID_ARG
+    assert call(p, n=0) == corr.CORR_E_INVALID_ARG
+    assert call(p, acc=2) == corr.CORR_E_INVALID_ARG
+    assert call(p, inv=4096) == corr.CORR_E_INVALID_ARG               # a scale with int8
+    assert call(p, n=corr.CORR_INT8_MAX_INTEGRATE + 1) == corr.CORR_E_OVERFLOW
+    assert call(corr.make_params(8, 2, 64, 1, "int8", layout="upper")) == corr.CORR_E_UNSUPPORTED
+    assert call(corr.make_params(3, 5, 64, 1)) == corr.CORR_E_INVALID_ARG
+    # one channel of 8192 inputs x 2048 int8 spectra needs 32 MiB + 256 bytes of staging
+    big = corr.make_params(4096, 2, 16, 1, "int8")
+    assert call(big, n=2048) == corr.CORR_E_UNSUPPORTED
+    assert "scratch" in corr.corr_last_error(None)
