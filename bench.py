@@ -78,8 +78,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-sub-array batched (persistent, graph-captured) section")
-    ap.add_argument("--batched-blocks-per-x", type=int, default=4,
-                    help="F-engine time blocks appended per batched X-engine launch")
+    ap.add_argument("--batched-blocks-per-x", type=int, default=8,
+                    help="F-engine time blocks appended per batched X-engine launch (8: the whole integration)")
     ap.add_argument("--batched-steps", type=int, default=8,
                     help="graph replays per integration in the batched section")
     ap.add_argument("--cpu-channels", type=int, default=16,
@@ -611,6 +611,18 @@ def run_batched(torch, corr, synth, steps_per_integration, blocks_per_x=4, reps=
         b.close()
         del volts, invs
     torch.cuda.empty_cache()
+    # integration against its roofline: the FP16 MFMA peak for the X-engine
+    # work, and the HBM bytes of the whole integration (voltages read and
+    # FP16 spectra written by the F-engines, spectra read and visibilities
+    # written by the X-engines, a read of the visibilities for every X call
+    # after the first)
+    integ_s = t_step * replays * 1e-3
+    cm_integ = cm_step * replays
+    x_calls = replays
+    v_bytes = sum(w.n_inputs * n * w.n_channels * 8 for w, n in zip(ws, ns)) * steps_per_integration
+    s_bytes = sum(w.n_inputs * w.n_channels * 4 * h for w, h in zip(ws, held)) * replays
+    a_bytes = sum(w.n_products * w.n_channels * 8 for w in ws)
+    hbm = v_bytes + 2 * s_bytes + a_bytes * (1 + 2 * (x_calls - 1))
     out = {
         "workload": "batched-64: 64 sub-arrays, stations log-uniform 16..512 x 2 pols, "
                     "channels 2^(8..12), integration 256..2048 (seed 5), FP16 in / FP32 accumulate",
@@ -629,8 +641,59 @@ def run_batched(torch, corr, synth, steps_per_integration, blocks_per_x=4, reps=
         "graph_step_tcmacs": cm_step / (t_step * 1e-3) / 1e12,
         "integration_ms": t_step * replays,
         "graph_steps_per_integration": replays,
+        "integration_roofline": {
+            "cmac": cm_integ, "tcmacs": cm_integ / integ_s / 1e12,
+            "mfma_frac": 8 * cm_integ / integ_s / 1e12 / PEAK[prec],
+            "hbm_bytes": hbm, "hbm_gbs": hbm / integ_s / 1e9, "hbm_frac": hbm / integ_s / 1e9 / HBM_PEAK_GBS,
+            "min_ms_at_peaks": 1e3 * max(8 * cm_integ / (PEAK[prec] * 1e12), hbm / (HBM_PEAK_GBS * 1e9))},
     }
     return out
+
+
+def run_batched_small(torch, corr, synth, reps=5):
+    """64 small sub-arrays (16..64 stations x 2 pols, 256..1024 channels,
+    integration 256..2048; seed 6), FP16: one batched persistent X-engine
+    launch against 64 per-array launches on the same held spectra."""
+    prec = "fp16"
+    ws = synth.batched_workloads(n_arrays=64, seed=6, max_channels_log2=10, min_stations=16, max_stations=64)
+    shapes = [(w.n_stations, w.n_pols, w.n_channels, w.n_integrate) for w in ws]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = corr.Batch(shapes, prec, stream=stream)
+        for i, w in enumerate(ws):
+            v = synth.voltages(w, device="cuda")
+            b.subs[i].fengine(v, w.n_integrate, torch.from_numpy(synth.inv_scale(w, prec)).to("cuda"))
+            del v
+        n = [w.n_integrate for w in ws]
+        b.xengine(n)
+
+        def per_array():
+            for sub, a in zip(b.subs, n):
+                sub.xengine(a)
+
+        per_array()
+        stream.synchronize()
+
+        def timed(fn, k):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(k):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / k
+
+        t_per = timed(per_array, reps)
+        t_bat = timed(lambda: b.xengine(n), reps)
+        b.close()
+    torch.cuda.empty_cache()
+    cm = sum(w.n_products * w.n_channels * w.n_integrate for w in ws)
+    return {"workload": "batched-small-64: 64 sub-arrays, stations log-uniform 16..64 x 2 pols, channels "
+                        "2^(8..10), integration 256..2048 (seed 6), FP16 in / FP32 accumulate",
+            "cmac_per_call": cm, "xengine_batched_ms": t_bat, "xengine_per_array_ms": t_per,
+            "xengine_batched_tcmacs": cm / (t_bat * 1e-3) / 1e12,
+            "xengine_per_array_tcmacs": cm / (t_per * 1e-3) / 1e12,
+            "batched_speedup_vs_per_array": t_per / t_bat}
 
 
 def main():
@@ -709,6 +772,18 @@ def main():
                      "step_tcmacs": cmacs / wall_f / 1e12, "timing": timing_f}
         log(f"{fp}: step {wall_f * 1e3:.3f} ms, F {f_ms_f:.3f} ms, X {x_ms_f:.3f} ms")
 
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cpu, errors = cpu_baseline(torch, oracle, synth, w, volts, results, chans)
+        for fp, e in errors.items():
+            if fp != prec:
+                forms[fp]["error_vs_float64"] = e
+        if prec in errors:
+            cpu["error_vs_float64_" + prec] = errors[prec]
+    del volts, out, results
+    torch.cuda.empty_cache()
+
     equal = None
     if not args.no_equal_accuracy:
         equal = run_equal_accuracy(torch, corr, synth.WORKLOADS[args.equal_workload])
@@ -727,21 +802,16 @@ def main():
 
     batched = None
     if not args.no_batched:
+        log("batched: 64 small sub-arrays")
+        small = run_batched_small(torch, corr, synth)
+        log(f"batched small: X {small['xengine_batched_ms']:.3f} ms (one launch) vs "
+            f"{small['xengine_per_array_ms']:.3f} ms (64 launches)")
         log("batched: 64 uneven sub-arrays")
         batched = run_batched(torch, corr, synth, args.batched_steps, args.batched_blocks_per_x)
         log(f"batched: X {batched['xengine_batched_ms']:.3f} ms (one launch) vs "
             f"{batched['xengine_per_array_ms']:.3f} ms (64 launches); graph step {batched['graph_step_ms']:.3f} ms; "
             f"integration {batched['integration_ms']:.1f} ms")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        cpu, errors = cpu_baseline(torch, oracle, synth, w, volts, results, chans)
-        for fp, e in errors.items():
-            if fp != prec:
-                forms[fp]["error_vs_float64"] = e
-        if prec in errors:
-            cpu["error_vs_float64_" + prec] = errors[prec]
+        batched["small_subarrays"] = small
 
     line = {
         "metric": METRIC,

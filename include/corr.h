@@ -314,14 +314,19 @@ CORR_API corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *ti
  * sub-arrays are drained by persistent X-engine launches -- one per block
  * size in use, so at most two -- from eight per-XCD work queues (channels
  * split evenly, largest items first, idle workgroups take work from the
- * other queues).  All sub-arrays share one precision and stream.  Each
+ * other queues).  All sub-arrays share one precision and stream (and one
+ * F-engine scratch, since their F-engines run in stream order).  Each
  * sub-array is an ordinary handle owned by the batch (corr_batch_get): use
  * corr_fengine, corr_dump_visibilities and corr_autotune on it as usual;
- * corr_destroy on it is CORR_E_STATE.  Sub-array accumulators are zeroed at
- * creation and a dump with reset zeroes them right away (a kernel, not a
- * memset), so a sequence of corr_fengine / corr_xengine_batched calls can be
- * captured into a HIP graph once a first corr_xengine_batched call with the
- * same n_spectra has been made outside the capture.  A changed work list
+ * corr_destroy on it is CORR_E_STATE.  Whether a sub-array's accumulators
+ * are logically zero is a flag in device memory: set at creation and by a
+ * dump with reset, cleared by the next X-engine call on the sub-array, whose
+ * items then write their sums instead of adding them (the accumulators are
+ * never cleared in memory, and the first call of an integration does not
+ * read them).  The flag is written by kernels, not memsets, so a sequence of
+ * corr_fengine / corr_xengine_batched calls (with dumps between them, if
+ * wanted) can be captured into a HIP graph once a first corr_xengine_batched
+ * call with the same n_spectra has been made outside the capture.  A changed work list
  * during capture is CORR_E_STATE; after it changes outside a capture,
  * capture again (an older graph then reads the new work plan, which stays
  * within every sub-array's buffers, but launches only the block sizes it

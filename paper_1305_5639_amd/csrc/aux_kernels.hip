@@ -147,7 +147,8 @@ __device__ __forceinline__ void pair_of(int layout, int N, int64_t b, int &i, in
 }
 
 __global__ void dump_convert_kernel(const int2 *__restrict__ acc, int2 *__restrict__ dst, int C, int N,
-                                    int layout, int order, int is_int) {
+                                    int layout, int order, int is_int, const int *__restrict__ zflag) {
+    const bool zero = zflag && *zflag;
     const int64_t Bl = (int64_t)N * (N + 1) / 2;
     const int64_t Bt = layout == 2 ? (int64_t)N * N : Bl;
     const int64_t total = Bt * C;
@@ -166,7 +167,7 @@ __global__ void dump_convert_kernel(const int2 *__restrict__ acc, int2 *__restri
         pair_of(layout, N, b, i, j);
         const bool mirrored = j > i;
         const int ii = mirrored ? j : i, jj = mirrored ? i : j;
-        int2 v = acc[(int64_t)k * Bl + (int64_t)ii * (ii + 1) / 2 + jj];
+        int2 v = zero ? make_int2(0, 0) : acc[(int64_t)k * Bl + (int64_t)ii * (ii + 1) / 2 + jj];
         if (mirrored) {  // C_ij = conj(C_ji)
             if (is_int)
                 v.y = -v.y;
@@ -187,6 +188,13 @@ __global__ void scale2_kernel(const float *__restrict__ inv, float *__restrict__
             s2[k] = 1.0f;
         }
     }
+}
+
+__global__ void dump_copy_kernel(const uint4 *__restrict__ acc, uint4 *__restrict__ dst, int64_t n_vec,
+                                 const int *__restrict__ zflag) {
+    const bool zero = *zflag != 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_vec; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = zero ? make_uint4(0, 0, 0, 0) : acc[e];
 }
 
 __global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n) {
@@ -262,11 +270,27 @@ hipError_t launch_export(int prec, int C, int N, int n_spectra, SpecLayout lay, 
 }
 
 hipError_t launch_dump_convert(int C, int N, int layout, int order, int is_int, const void *acc, void *dst,
-                               hipStream_t stream) {
+                               hipStream_t stream, const int *zflag) {
     const int64_t Bt = layout == 2 ? (int64_t)N * N : (int64_t)N * (N + 1) / 2;
     hipLaunchKernelGGL(dump_convert_kernel, dim3(grid_for(Bt * C)), dim3(kThreads), 0, stream,
-                       static_cast<const int2 *>(acc), static_cast<int2 *>(dst), C, N, layout, order, is_int);
+                       static_cast<const int2 *>(acc), static_cast<int2 *>(dst), C, N, layout, order, is_int, zflag);
     return hipGetLastError();
+}
+
+hipError_t launch_dump_copy(const void *acc, void *dst, int64_t n_words, const int *zflag, hipStream_t stream) {
+    // accumulators are 8-byte pairs, C * B of them; copy as 16-byte vectors
+    // and finish an odd pair with the zero flag as a 2-word tail
+    const int64_t n_vec = n_words / 4;
+    hipLaunchKernelGGL(dump_copy_kernel, dim3(grid_for(n_vec)), dim3(kThreads), 0, stream,
+                       static_cast<const uint4 *>(acc), static_cast<uint4 *>(dst), n_vec, zflag);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && n_words % 4) {
+        hipLaunchKernelGGL(dump_convert_kernel, dim3(1), dim3(kThreads), 0, stream,
+                           static_cast<const int2 *>(acc) + 2 * n_vec, static_cast<int2 *>(dst) + 2 * n_vec,
+                           1, 1, 0, 0, 0, zflag);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_scale2(int C, const float *inv_scale, float *scale2, hipStream_t stream) {

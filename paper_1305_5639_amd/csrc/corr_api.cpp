@@ -38,6 +38,7 @@ struct corr_ctx {
     float *unit_scale = nullptr;       // C ones: the F-engine's scale when the caller gives none
     void *gscr = nullptr;             // F-engine chunk scratch (kGatherMinC channels and up)
     int64_t gscr_bytes = 0;
+    bool owns_gscr = true;            // false: the batch's shared scratch
     float *scale2 = nullptr;          // s_k^2 of the F-engine's spectra
     float *scale2_user = nullptr;     // s_k^2 of caller spectra
     void *dump_tmp = nullptr;         // staging for converted dumps to host
@@ -46,7 +47,8 @@ struct corr_ctx {
     int64_t n_integrated = 0;         // spectra integrated since the last reset
     bool acc_zero = true;             // accumulators logically zero
     int tile = 0;                     // X-engine block size; 0 = by N
-    bool batch_member = false;        // owned by a corr_batch (eager reset)
+    bool batch_member = false;        // owned by a corr_batch
+    int *zflag = nullptr;             // batch members: device "zero since reset" flag
     std::string err;
 };
 
@@ -59,12 +61,17 @@ struct corr_batch {
     uint8_t *h_plan = nullptr;        // pinned staging of the plan
     std::vector<uint8_t> last;        // plan last uploaded
     unsigned int *d_counter = nullptr;  // per-XCD work counters of both block-size groups
+    void *d_gscr = nullptr;           // F-engine scratch shared by the sub-arrays (one stream)
+    int *d_zflag = nullptr;           // one "zero since reset" flag per sub-array
     std::string err;
 };
 
 namespace {
 
 thread_local std::string g_err;
+// Set while corr_create_batched creates its sub-arrays: they share one
+// F-engine scratch owned by the batch instead of each allocating its own.
+thread_local bool g_no_own_scratch = false;
 
 corr_status fail(corr_ctx *h, corr_status s, const std::string &msg) {
     if (h)
@@ -245,7 +252,7 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
     const size_t acc_bytes = (size_t)C * B * 8;
     const size_t small_bytes = (size_t)C * 8 + 2 * (size_t)C * 4;
     const size_t dump_bytes = default_dump(params) ? 0 : (size_t)corr_visibility_bytes(params);
-    const size_t gscr_bytes = (size_t)gather_scratch_bytes(C, N, n_tb_cap);
+    const size_t gscr_bytes = g_no_own_scratch ? 0 : (size_t)gather_scratch_bytes(C, N, n_tb_cap);
     const size_t need = spec_bytes + acc_bytes + small_bytes + dump_bytes + gscr_bytes;
     if (params->device_mem_cap && need > params->device_mem_cap) {
         char b[160];
@@ -337,7 +344,7 @@ static void destroy_ctx(corr_ctx *h) {
     (void)hipFree(h->twiddle);
     (void)hipFree(h->twiddle2n);
     (void)hipFree(h->unit_scale);
-    (void)hipFree(h->gscr);
+    if (h->owns_gscr) (void)hipFree(h->gscr);
     (void)hipFree(h->scale2);
     (void)hipFree(h->scale2_user);
     (void)hipFree(h->dump_tmp);
@@ -479,8 +486,9 @@ corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t n_spectra
     const float *s2 = nullptr;
     const corr_status st = prepare_x(h, d_spectra, n_spectra, d_inv_scale, &s2);
     if (st != CORR_OK) return st;
-    const hipError_t e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->spec, h->lay, s2,
-                                        h->acc, h->acc, h->acc_zero ? 1 : 0, h->stream);
+    hipError_t e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, n_spectra, h->spec, h->lay, s2, h->acc,
+                                  h->acc, h->acc_zero ? 1 : 0, h->stream, h->zflag);
+    if (e == hipSuccess && h->zflag) e = launch_set_flag(h->zflag, 0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
     h->acc_zero = false;
     h->n_integrated += n_spectra;
@@ -535,6 +543,31 @@ corr_status corr_dump_visibilities(corr_handle h, void *dst, int32_t dst_on_devi
     if (dst_on_device && !aligned(dst, 8)) return fail(h, CORR_E_INVALID_ARG, "dst must be 8-byte aligned");
     const size_t bytes = (size_t)corr_visibility_bytes(&h->p);
     hipError_t e;
+    if (h->zflag) {
+        // batch member: whether the accumulators are logically zero is the
+        // device flag's to say (graph replays do not pass through the host)
+        void *target = dst;
+        if (!dst_on_device) {
+            if (!h->dump_tmp && (e = hipMalloc(&h->dump_tmp, bytes)) != hipSuccess)
+                return hip_fail(h, e, "hipMalloc dump staging");
+            target = h->dump_tmp;
+        }
+        if (default_dump(&h->p) && aligned(target, 16))
+            e = launch_dump_copy(h->acc, target, (int64_t)(bytes / 4), h->zflag, h->stream);
+        else
+            e = launch_dump_convert(h->C, h->N, h->p.layout, h->p.order, h->prec == P_INT8 ? 1 : 0, h->acc, target,
+                                    h->stream, h->zflag);
+        if (e != hipSuccess) return hip_fail(h, e, "dump launch");
+        if (reset && (e = launch_set_flag(h->zflag, 1, h->stream)) != hipSuccess) return hip_fail(h, e, "flag launch");
+        if (!dst_on_device) {
+            if ((e = hipMemcpyAsync(dst, target, bytes, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+                return hip_fail(h, e, "hipMemcpyAsync dump");
+            if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+        }
+        if (reset) h->n_integrated = 0;
+        h->err.clear();
+        return CORR_OK;
+    }
     if (h->acc_zero) {
         if (dst_on_device) {
             e = launch_zero(dst, (int64_t)(bytes / 4), h->stream);
@@ -567,14 +600,7 @@ corr_status corr_dump_visibilities(corr_handle h, void *dst, int32_t dst_on_devi
         }
     }
     if (reset) {
-        if (h->batch_member) {
-            // eager: the accumulators are zero in memory, so the batched
-            // X-engine can always accumulate (graph-replay friendly)
-            e = launch_zero(h->acc, (int64_t)(h->acc_bytes / 4), h->stream);
-            if (e != hipSuccess) return hip_fail(h, e, "zero launch");
-        } else {
-            h->acc_zero = true;
-        }
+        h->acc_zero = true;
         h->n_integrated = 0;
     }
     h->err.clear();
@@ -691,6 +717,8 @@ static void destroy_batch(corr_batch *b) {
     for (corr_ctx *h : b->subs) destroy_ctx(h);
     (void)hipFree(b->d_plan);
     (void)hipFree(b->d_counter);
+    (void)hipFree(b->d_zflag);
+    (void)hipFree(b->d_gscr);
     if (b->h_plan) (void)hipHostFree(b->h_plan);
     delete b;
 }
@@ -700,6 +728,7 @@ corr_status corr_create_batched(const corr_params *params, int32_t n, void *hip_
     if (n < 1 || n > 65536) return fail(nullptr, CORR_E_INVALID_ARG, "n must be in 1..65536");
     std::string msg;
     uint64_t need = 0;
+    int64_t gscr_bytes = 0;                  // one scratch for all: the largest any sub-array needs
     for (int i = 0; i < n; ++i) {
         corr_status s = check_params(&params[i], msg);
         if (s != CORR_OK) return fail(nullptr, s, "sub-array " + std::to_string(i) + ": " + msg);
@@ -709,9 +738,11 @@ corr_status corr_create_batched(const corr_params *params, int32_t n, void *hip_
         const int TB = time_block(params[i].precision);
         need += (uint64_t)spec_buffer_bytes(params[i].n_channels, (int)N, (params[i].n_integrate + TB - 1) / TB,
                                             elem_bytes(params[i].precision)) +
-                (uint64_t)gather_scratch_bytes(params[i].n_channels, (int)N, (params[i].n_integrate + TB - 1) / TB) +
                 (uint64_t)params[i].n_channels * (N * (N + 1) / 2) * 8;
+        gscr_bytes = std::max(gscr_bytes, gather_scratch_bytes(params[i].n_channels, (int)N,
+                                                               (params[i].n_integrate + TB - 1) / TB));
     }
+    need += (uint64_t)gscr_bytes;
     if (params[0].device_mem_cap && need > params[0].device_mem_cap)
         return fail(nullptr, CORR_E_NOMEM, "batch needs " + std::to_string(need) + " bytes, over the cap");
     corr_batch *b = new (std::nothrow) corr_batch();
@@ -722,19 +753,38 @@ corr_status corr_create_batched(const corr_params *params, int32_t n, void *hip_
         corr_params p = params[i];
         p.device_mem_cap = 0;
         corr_handle h = nullptr;
+        g_no_own_scratch = true;
         corr_status s = corr_create(&p, hip_stream, &h);
+        g_no_own_scratch = false;
         if (s != CORR_OK) {
             std::string m = "sub-array " + std::to_string(i) + ": " + g_err;
             destroy_batch(b);
             return fail(nullptr, s, m);
         }
         h->batch_member = true;
-        h->acc_zero = false;
+        h->acc_zero = false;                     // the device flag decides
         b->subs.push_back(h);
-        hipError_t e = launch_zero(h->acc, (int64_t)(h->acc_bytes / 4), b->stream);
-        if (e != hipSuccess) {
-            destroy_batch(b);
-            return fail(nullptr, CORR_E_HIP, std::string("zero launch: ") + hipGetErrorString(e));
+    }
+    // every sub-array starts logically zero: its flag is set, its
+    // accumulators are never cleared in memory
+    hipError_t ez = hipMalloc(&b->d_zflag, (size_t)n * sizeof(int));
+    if (ez == hipSuccess)
+        ez = hipMemcpy(b->d_zflag, std::vector<int>(n, 1).data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice);
+    if (ez != hipSuccess) {
+        destroy_batch(b);
+        return fail(nullptr, CORR_E_HIP, std::string("batch flags: ") + hipGetErrorString(ez));
+    }
+    for (int i = 0; i < n; ++i) b->subs[i]->zflag = b->d_zflag + i;
+    if (gscr_bytes && (ez = hipMalloc(&b->d_gscr, (size_t)gscr_bytes)) != hipSuccess) {
+        destroy_batch(b);
+        return fail(nullptr, ez == hipErrorOutOfMemory ? CORR_E_NOMEM : CORR_E_HIP,
+                    std::string("batch F-engine scratch: ") + hipGetErrorString(ez));
+    }
+    for (corr_ctx *h : b->subs) {
+        h->owns_gscr = false;
+        if (gather_scratch_bytes(h->C, h->N, h->n_tb_cap)) {
+            h->gscr = b->d_gscr;
+            h->gscr_bytes = gscr_bytes;
         }
     }
     int dev = 0, cus = 0;
@@ -809,7 +859,8 @@ corr_status corr_xengine_batched(corr_batch_handle b, const int32_t *n_spectra) 
             x.tile = effective_tile(h);
             const int nb = (h->N + x.tile - 1) / x.tile;
             x.n_tiles = nb * (nb + 1) / 2;
-            x.first_call = 0;                 // batch accumulators are always zero in memory after reset
+            x.first_call = 0;
+            x.zflag = h->zflag;               // set: write instead of add (cleared after the launch)
             for (int xc = 0; xc < kXcds; ++xc) {
                 x.qbegin[xc] = q[g].qlen[xc];
                 const int c_lo = xc * h->C / kXcds, c_hi = (xc + 1) * h->C / kXcds;

@@ -109,11 +109,16 @@ hipError_t launch_fengine_real8(int prec, int C, int N, const int8_t *samples, i
 // buffer into acc (spectra past n_spectra in the last time block are masked to
 // zero), with square blocks of `tile` (64 or 128) inputs.  scale2 (float
 // forms, may be null = 1): per-channel s_k^2 applied to the integrated
-// products.  first_call = 1 writes instead of read-modify-write.  The sums so
-// far are read from acc_in (acc itself, or the accumulators when acc is a
-// dump destination in the accumulator layout).
+// products.  first_call = 1 writes instead of read-modify-write; so does a
+// set device flag *zflag (zflag may be null).  The sums so far are read from
+// acc_in (acc itself, or the accumulators when acc is a dump destination in
+// the accumulator layout).
 hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
-                          const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream);
+                          const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream,
+                          const int *zflag = nullptr);
+
+// Write v to the device int *flag (a kernel, so graphs replay it).
+hipError_t launch_set_flag(int *flag, int v, hipStream_t stream);
 
 // Rectangle X-engine: rows [r0, r0 + ni) against columns [c0, c0 + nj) of the
 // held spectra (disjoint ranges), into out [C][ni][nj] (re, im) pairs, written
@@ -135,6 +140,7 @@ struct XDesc {
     const uint8_t *spec;
     void *acc;
     const float *scale2;
+    int *zflag;                       // the sub-array's "zero since reset" flag (device)
     int64_t k_stride;                 // SpecLayout::ks
     int64_t tb_stride;                // SpecLayout::ts
     int64_t B;
@@ -159,7 +165,9 @@ struct XQueue {
 // through per-queue atomic counters.  A 16-thread kernel zeroes the 2 x 8 counters
 // (2 * kXcds * kCounterStride words), then one persistent launch per group in
 // launch_group (bit 0: 64-input, bit 1: 128-input) runs at that block size's
-// occupancy.
+// occupancy, and a last one-workgroup kernel clears the zero flag of every
+// sub-array in the plan (an item whose flag is set writes its sums instead of
+// adding to the accumulators).
 hipError_t launch_xengine_batched(int prec, const XQueue *d_plan, const XDesc *d_desc, int launch_group,
                                   unsigned int *counters, int num_cus, hipStream_t stream);
 
@@ -177,9 +185,13 @@ hipError_t launch_ingest_channels(int prec, int C, int k0, int nk, int N, int n_
 // Dump conversion from the lower-triangle channel-major accumulators into a
 // layout (0 lower, 1 upper, 2 full) and order (0 chan-major, 1 baseline-major).
 // Entries are 8-byte (re, im) pairs; is_int selects int32 negation for the
-// conjugate of mirrored products.
+// conjugate of mirrored products.  A set device flag *zflag (zflag may be
+// null) means the accumulators are logically zero: zeros are written.
 hipError_t launch_dump_convert(int C, int N, int layout, int order, int is_int,
-                               const void *acc, void *dst, hipStream_t stream);
+                               const void *acc, void *dst, hipStream_t stream, const int *zflag = nullptr);
+
+// dst = acc (n_words 32-bit words), or zeros when *zflag is set.
+hipError_t launch_dump_copy(const void *acc, void *dst, int64_t n_words, const int *zflag, hipStream_t stream);
 
 // s_k^2 = 1 / inv_s[k]^2 (or 1 when inv_s is null) into scale2[C].
 hipError_t launch_scale2(int C, const float *inv_scale, float *scale2, hipStream_t stream);

@@ -38,13 +38,27 @@
 namespace corr {
 namespace {
 
+// The complex FP32 form at 2048 and 4096 channels stores straight into the
+// held rows from 512-thread workgroups (8 or 4 spectra each, so 32- or
+// 16-byte pieces of each row) instead of through the chunked gather: on 2^28
+// samples 1.83 -> 1.64 ms at 2048 and 2.05 -> 1.93 ms at 4096 channels, and
+// 30.7 -> 28.6 ms for 1024 inputs x 4096 channels x 1024 spectra.  At 8192
+// channels (2 spectra per workgroup) the gather stays faster (2.36 against
+// 2.94 ms), and so it does for every low-precision form, whose larger
+// workgroups measured 35-75% slower.
+template <int C, int PREC, bool REAL>
+constexpr bool fp32_direct() {
+    return !REAL && PREC == P_FP32 && (C == 2048 || C == 4096);
+}
+
 // Threads per workgroup: 256, or 512 for the int8 / FP8 complex forms at C =
 // 512 and 1024, where twice the spectra per workgroup (so half as many
 // partial output rows) measured 3-10% faster on 2^28 samples; at 256 channels
-// they gained nothing.  From 2048 channels the chunked store and gather
-// leave no partial rows to save.
+// they gained nothing; and 512 for fp32_direct.  From 2048 channels the
+// chunked store and gather leave no partial rows to save.
 template <int C, int PREC, bool REAL>
 constexpr int threads() {
+    if (fp32_direct<C, PREC, REAL>()) return 512;
     return (!REAL && (PREC == P_INT8 || PREC == P_FP8) && (C == 512 || C == 1024)) ? 512 : 256;
 }
 
@@ -540,7 +554,7 @@ __global__ __launch_bounds__((threads<C, PREC, REAL>())) __attribute__((amdgpu_w
     constexpr bool SCALE_TEST = !REAL && (PREC == P_FP32 || PREC == P_FP16);
     // GATHER: stores go to the chunk scratch (passed as spec) in natural
     // order, [workgroup][plane][channel][spectrum], contiguous per workgroup.
-    constexpr bool GATHER = C >= kGatherMinC;
+    constexpr bool GATHER = C >= kGatherMinC && !fp32_direct<C, PREC, REAL>();
     static_assert(!GATHER || T <= TB, "a gathered workgroup must lie within one time block");
     constexpr int LF = SPLIT ? 1 : 2;                  // floats per LDS element
     constexpr int NPL = 2 * C * S <= T * CP * 4 * LF ? 2 : 1;   // planes staged at a time
@@ -674,7 +688,7 @@ hipError_t launch_c(int N, const void *in, int64_t ld, int n_spectra, const floa
                            n_valid_pad, (int)n_work, inv_scale, tw, tw2, dst, lay.ks, lay.ts, first_tb);
         return hipGetLastError();
     };
-    if constexpr (C < kGatherMinC) {
+    if constexpr (C < kGatherMinC || fp32_direct<C, PREC, REAL>()) {
         return run(in, N, n_spectra, static_cast<uint8_t *>(spec), tb0);
     } else {
         // Chunks of whole time blocks of all inputs, or of one time block of

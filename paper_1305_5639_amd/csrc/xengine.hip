@@ -424,11 +424,14 @@ __device__ __forceinline__ void tri_block(int t, int &bi, int &bj) {
     bj = t - b * (b + 1) / 2;
 }
 
+// zflag (may be null): a device flag that, when set, makes this the first
+// call of an integration whatever first_call says (the accumulators of a
+// batch sub-array are then logically zero, whatever they hold).
 template <int PREC, int TILE>
 __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_waves_per_eu(4))) void xengine_kernel(
     const uint8_t *__restrict__ spec, int N, int n_tiles, int n_work, int n_tb, int tv,
     int64_t k_stride, int64_t t_stride, const float *__restrict__ scale2, void *__restrict__ acc_out,
-    const void *acc_in, int64_t B, int first_call) {
+    const void *acc_in, int64_t B, int first_call, const int *__restrict__ zflag) {
     __shared__ __attribute__((aligned(16))) uint8_t smem[ring_bytes(TILE)];
     const int per = (n_work + 7) / 8;
     const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -436,8 +439,9 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
     const int k = w / n_tiles;
     int bi, bj;
     tri_block(w % n_tiles, bi, bj);
+    const int fc = zflag && *zflag ? 1 : first_call;
     tile<PREC, TILE>(smem, spec + (int64_t)k * k_stride, t_stride, N, n_tb, tv, bi * TILE, bj * TILE, k, scale2,
-                     acc_out, acc_in, B, first_call, threadIdx.x);
+                     acc_out, acc_in, B, fc, threadIdx.x);
 }
 
 // Rectangle X-engine: rows [r0, r0 + ni) against columns [c0, c0 + nj) in
@@ -486,16 +490,29 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
         // selects) in scalar registers
         int64_t item = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_item);
         __syncthreads();                                // s_item free for reuse
+        // the descriptor of the last item and its item range in this queue:
+        // a workgroup's items rise, so most items reuse it without a search
+        int cur = 0, cur_fc = 0;
+        int64_t c_lo = 1, c_hi = 0;
         while (item < qlen) {
             // take the next ticket now; its latency overlaps this item's loads
             unsigned int next = 0;
             if (tid == 0) next = atomicAdd(cnt, 1u);
-            int lo = 0, hi = n_desc - 1;                // last descriptor with qbegin[x] <= item
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (desc[mid].qbegin[x] <= item) lo = mid; else hi = mid - 1;
+            if (item < c_lo || item >= c_hi) {
+                int lo = 0, hi = n_desc - 1;            // last descriptor with qbegin[x] <= item
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (desc[mid].qbegin[x] <= item) lo = mid; else hi = mid - 1;
+                }
+                cur = lo;
+                c_lo = desc[lo].qbegin[x];
+                c_hi = lo + 1 < n_desc ? desc[lo + 1].qbegin[x] : qlen;
+                // the sub-array's flag is cleared only after the launch, so
+                // every item of it reads the same value
+                const int *zf = desc[lo].zflag;
+                cur_fc = zf && *(const __attribute__((address_space(1))) int *)zf ? 1 : desc[lo].first_call;
             }
-            const XDesc &d = desc[lo];
+            const XDesc &d = desc[cur];
             const int64_t local = item - d.qbegin[x];
             const int k = x * d.C / kXcds + (int)(local / d.n_tiles);
             int bi, bj;
@@ -507,7 +524,7 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
             asm volatile("" : "+v"(t));
             tile<PREC, TILE>(smem, d.spec + (int64_t)k * d.k_stride, d.tb_stride, d.N, d.n_tb, d.tv, bi * TILE,
                              bj * TILE, k,
-                             d.scale2, d.acc, d.acc, d.B, d.first_call, t);
+                             d.scale2, d.acc, d.acc, d.B, cur_fc, t);
             if (tid == 0) s_item = next;
             __syncthreads();                            // also: every wave is done with smem
             item = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_item);
@@ -518,9 +535,19 @@ __global__ __launch_bounds__(WaveGrid<TILE>::THREADS) __attribute__((amdgpu_wave
 
 __global__ void reset_counters_kernel(unsigned int *counter) { counter[threadIdx.x * kCounterStride] = 0u; }
 
+// After a batched launch: clear the zero flag of every sub-array in the plan.
+__global__ void clear_flags_kernel(const XQueue *__restrict__ plan, const XDesc *__restrict__ desc) {
+    const int n = plan[0].n_desc + plan[1].n_desc;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (desc[i].zflag) *desc[i].zflag = 0;
+}
+
+__global__ void set_flag_kernel(int *flag, int v) { *flag = v; }
+
 template <int PREC, int TILE>
 hipError_t launch_x(int C, int N, int n_spectra, const void *spec, SpecLayout lay,
-                    const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream) {
+                    const float *scale2, void *acc, const void *acc_in, int first_call, const int *zflag,
+                    hipStream_t stream) {
     const int TB = time_block(PREC);
     const int n_tb = (n_spectra + TB - 1) / TB;
     const int tv = n_spectra - (n_tb - 1) * TB;
@@ -532,15 +559,18 @@ hipError_t launch_x(int C, int N, int n_spectra, const void *spec, SpecLayout la
     const int64_t B = (int64_t)N * (N + 1) / 2;
     hipLaunchKernelGGL((xengine_kernel<PREC, TILE>), dim3(grid), dim3(WaveGrid<TILE>::THREADS), 0, stream,
                        static_cast<const uint8_t *>(spec), N, n_tiles, (int)n_work, n_tb, tv, lay.ks, lay.ts,
-                       scale2, acc, acc_in, B, first_call);
+                       scale2, acc, acc_in, B, first_call, zflag);
     return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t launch_xp(int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
-                     const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream) {
-    if (tile == 64) return launch_x<PREC, 64>(C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, stream);
-    if (tile == 128) return launch_x<PREC, 128>(C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, stream);
+                     const float *scale2, void *acc, const void *acc_in, int first_call, const int *zflag,
+                     hipStream_t stream) {
+    if (tile == 64)
+        return launch_x<PREC, 64>(C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, zflag, stream);
+    if (tile == 128)
+        return launch_x<PREC, 128>(C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, zflag, stream);
     return hipErrorInvalidValue;
 }
 
@@ -588,8 +618,9 @@ hipError_t launch_xengine_rect(int prec, int tile, int C, int N, int n_spectra, 
 }
 
 hipError_t launch_xengine(int prec, int tile, int C, int N, int n_spectra, const void *spec, SpecLayout lay,
-                          const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream) {
-#define CORR_X_ARGS tile, C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, stream
+                          const float *scale2, void *acc, const void *acc_in, int first_call, hipStream_t stream,
+                          const int *zflag) {
+#define CORR_X_ARGS tile, C, N, n_spectra, spec, lay, scale2, acc, acc_in, first_call, zflag, stream
     switch (prec) {
     case P_FP32: return launch_xp<P_FP32>(CORR_X_ARGS);
     case P_FP16: return launch_xp<P_FP16>(CORR_X_ARGS);
@@ -633,7 +664,16 @@ hipError_t launch_xengine_batched(int prec, const XQueue *d_plan, const XDesc *d
         e = launch_batched_p<128>(prec, d_plan + 1, d_desc, counters + kXcds * kCounterStride, g128, stream);
     if (e == hipSuccess && (launch_group & 1))
         e = launch_batched_p<64>(prec, d_plan, d_desc, counters, g64, stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(256), 0, stream, d_plan, d_desc);
+        e = hipGetLastError();
+    }
     return e;
+}
+
+hipError_t launch_set_flag(int *flag, int v, hipStream_t stream) {
+    hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, stream, flag, v);
+    return hipGetLastError();
 }
 
 }  // namespace corr

@@ -217,3 +217,32 @@ def test_batched_fp16_seed5_subarrays_vs_oracle():
             assert en.max() < 1e-3, i
             vs[i] = None
             torch.cuda.empty_cache()
+
+
+def test_batch_member_per_array_calls_and_resets():
+    """Per-array X-engine calls on batch sub-arrays follow the same device
+    "zero since reset" flag as the batched launch: a reset makes the next call
+    write, further calls add, and a dump before any call reads zeros."""
+    say("batch member per-array calls and resets")
+    shapes = SHAPES[:3]
+    vs, invs = _batch_inputs("int8", shapes, seed=30)
+    n = [A for (_, _, _, A) in shapes]
+    with corr.Batch(shapes, "int8") as b:
+        for i, sub in enumerate(b.subs):
+            assert not sub.dump(reset=False).cpu().numpy().any()          # logically zero at creation
+            sub.fengine(torch.from_numpy(vs[i]).to(DEV), n[i], torch.from_numpy(invs[i]).to(DEV))
+        refs = [oracle.xengine_i8(spectra_akp_to_apk(sub.spectra().cpu().numpy())) for sub in b.subs]
+        for i, sub in enumerate(b.subs):
+            sub.xengine(n[i])
+            sub.xengine(n[i])
+        b.xengine(n)                                                     # three integrations in all
+        for i, sub in enumerate(b.subs):
+            assert np.array_equal(sub.dump(reset=True).cpu().numpy().astype(np.int64), 3 * refs[i]), i
+            assert not sub.dump(reset=False).cpu().numpy().any(), i      # reset: zeros until the next call
+            host = np.empty(sub.visibility_shape(), dtype=np.int32)
+            sub.dump(host, reset=False)
+            assert not host.any(), i
+        b.xengine(n)
+        for i, sub in enumerate(b.subs):
+            sub.xengine(n[i])
+            assert np.array_equal(sub.dump(reset=True).cpu().numpy().astype(np.int64), 2 * refs[i]), i
