@@ -419,6 +419,49 @@ def run_config_steps(torch, corr, synth, reps=3):
     return res
 
 
+def run_fused_fx(torch, corr, synth, reps=3):
+    """F and X fused over time chunks (corr_fx) on 256 x 2 inputs, 2048
+    channels, 2048 spectra, int8, beside the unfused F + X.  A chunk of
+    64 spectra (one time block, 134 MB of int8 spectra) fits the memory-side
+    cache; every chunk after the first reads and writes the 2.15 GB of
+    accumulators once more."""
+    w = synth.WORKLOADS["int8-256x2-c2048"]
+    N, C, A = w.n_inputs, w.n_channels, w.n_integrate
+    volts = synth.voltages(w, device="cuda")
+    inv = torch.from_numpy(synth.inv_scale(w, "int8")).to("cuda")
+    acc_bytes = C * N * (N + 1) // 2 * 8
+    res = {"workload": f"{w.name}: int8", "accumulator_bytes": acc_bytes}
+    dst = None
+    for chunk in (64, 256, 1024, A):
+        c = corr.Correlator(w.n_stations, w.n_pols, C, chunk, "int8")
+        dst = c.new_visibilities()
+        fn = (lambda: (c.fengine(volts, A, inv), c.xengine(A))) if chunk == A else (lambda: c.fx(volts, A, inv, chunk))
+        fn()
+        c.dump(dst, reset=True)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+            c.dump(dst, reset=True)
+        ms = float(np.median(ts))
+        n_chunks = -(-A // chunk)
+        key = "unfused" if chunk == A else f"chunk_{chunk}"
+        res[key] = {"chunk_spectra": chunk, "chunks": n_chunks, "fx_ms": ms, "tcmacs": w.cmacs / (ms * 1e-3) / 1e12,
+                    "extra_accumulator_bytes": 2 * (n_chunks - 1) * acc_bytes,
+                    "spectra_bytes_per_chunk": N * C * 2 * min(chunk, A)}
+        log(f"fused FX int8 chunk {chunk}: {ms:.2f} ms")
+        c.close()
+        del dst
+        torch.cuda.empty_cache()
+    del volts
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_paper_workload(torch, corr, synth, reps=3):
     """The paper's own test streams (Section 5): 8-bit real samples, transform
     length 256 (128 channels), 1024 spectra, 128 to 3072 streams; the
@@ -796,6 +839,10 @@ def main():
     if not args.no_configs:
         configs = run_config_steps(torch, corr, synth)
 
+    fused = None
+    if not args.no_configs:
+        fused = run_fused_fx(torch, corr, synth)
+
     paper = None
     if not args.no_paper:
         paper = run_paper_workload(torch, corr, synth)
@@ -842,6 +889,7 @@ def main():
         "xengine_shapes": shapes,
         "batched": batched,
         "config_steps": configs,
+        "fused_fx": fused,
         "paper_workload": paper,
         "cpu_baseline": cpu,
     }

@@ -220,6 +220,27 @@ CORR_API corr_status corr_xengine(corr_handle h, const void *d_spectra, int32_t 
                          const float *d_inv_scale);
 
 /*
+ * F and X fused over time chunks (Eq. 1 then Eq. 2): the n_spectra spectra
+ * of d_volts (as for corr_fengine) are channelised and correlated
+ * chunk_spectra at a time -- the F-engine writes a chunk into the first
+ * chunk_spectra slots of the held spectra and the X-engine adds it into the
+ * accumulators right away -- so a chunk small enough stays in the
+ * memory-side cache between the two (the paper keeps its F output close to
+ * the X-engine and ships it packed, Section 6).  The result is that of one
+ * corr_fengine + corr_xengine over the whole integration (bit for bit for
+ * CORR_INT8; the float forms sum in another order), and n_spectra may exceed
+ * n_integrate.  Afterwards the held spectra are the last chunk's.
+ *   chunk_spectra : a multiple of the time block (16 FP32, 32 FP16, 64 FP8 /
+ *                   int8 spectra), at most n_integrate.
+ * Every chunk reads and writes the accumulators once more, which is why the
+ * unfused corr_fengine + corr_xengine is the faster path on the configured
+ * workloads.  Errors as corr_fengine and corr_xengine (CORR_E_STATE for batch
+ * sub-arrays).
+ */
+CORR_API corr_status corr_fx(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
+                             const float *d_inv_scale, int32_t chunk_spectra);
+
+/*
  * The last X-engine call of an integration fused with its dump: as
  * corr_xengine, but the integrated visibilities (the accumulators' sums plus
  * this call's) are written straight to d_dst, in the dump's lower-triangle,

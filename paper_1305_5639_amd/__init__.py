@@ -12,5 +12,5 @@ from .corr import (  # noqa: F401
     corr_get_counts, corr_last_error, corr_n_products, corr_params, corr_spectra_bytes,
     corr_status_string, corr_visibility_bytes, corr_xengine, lib, make_params, corr_set_tile,
     corr_autotune, corr_create_batched, corr_batch_get, corr_xengine_batched, corr_destroy_batched,
-    corr_xengine_rect, corr_fengine_real8, corr_xengine_dump, corr_xengine_noalloc,
+    corr_xengine_rect, corr_fengine_real8, corr_xengine_dump, corr_xengine_noalloc, corr_fx,
 )

@@ -44,7 +44,7 @@ ABI_FUNCTIONS = (
     "corr_copy_spectra", "corr_get_counts", "corr_status_string", "corr_last_error",
     "corr_set_tile", "corr_autotune", "corr_create_batched", "corr_batch_get",
     "corr_xengine_batched", "corr_destroy_batched", "corr_xengine_rect", "corr_fengine_real8",
-    "corr_fengine_at", "corr_fengine_real8_at", "corr_xengine_dump", "corr_xengine_noalloc",
+    "corr_fengine_at", "corr_fengine_real8_at", "corr_xengine_dump", "corr_xengine_noalloc", "corr_fx",
 )
 
 
@@ -110,9 +110,10 @@ def lib() -> ctypes.CDLL:
         L.corr_destroy_batched.argtypes = [P]
         L.corr_xengine_rect.argtypes = [P, i32, i32, i32, i32, i32, P, i32]
         L.corr_xengine_noalloc.argtypes = [PP, P, i32, P, P, i32, P]
+        L.corr_fx.argtypes = [P, P, i64, i32, P, i32]
         for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_fengine_real8", "corr_fengine_at",
                   "corr_fengine_real8_at", "corr_xengine", "corr_xengine_dump",
-                  "corr_xengine_rect", "corr_xengine_noalloc",
+                  "corr_xengine_rect", "corr_xengine_noalloc", "corr_fx",
                   "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts", "corr_set_tile",
                   "corr_autotune", "corr_create_batched", "corr_batch_get", "corr_xengine_batched",
                   "corr_destroy_batched"):
@@ -250,6 +251,11 @@ def corr_xengine_rect(h, i0: int, ni: int, j0: int, nj: int, n_spectra: int, out
                                    int(bool(accumulate))), "corr_xengine_rect", h)
 
 
+def corr_fx(h, volts, n_spectra: int, inv_scale, chunk_spectra: int, ld_samples: int | None = None) -> None:
+    x, ld = _rows(volts, ld_samples)
+    _check(lib().corr_fx(h, x, int(ld), int(n_spectra), _ptr(inv_scale), int(chunk_spectra)), "corr_fx", h)
+
+
 def corr_xengine_noalloc(params: corr_params, spectra, n_spectra: int, inv_scale, vis, accumulate: bool = False,
                          stream=None) -> None:
     _check(lib().corr_xengine_noalloc(ctypes.byref(params), _ptr(spectra), int(n_spectra), _ptr(inv_scale),
@@ -331,6 +337,11 @@ class Correlator:
 
     def xengine(self, n_spectra, spectra=None, inv_scale=None):
         corr_xengine(self.handle, spectra, n_spectra, inv_scale)
+
+    def fx(self, volts, n_spectra, inv_scale=None, chunk_spectra=None, ld_samples=None):
+        """F and X fused over time chunks (corr_fx)."""
+        corr_fx(self.handle, volts, n_spectra, inv_scale,
+                self.params.n_integrate if chunk_spectra is None else chunk_spectra, ld_samples)
 
     def xengine_dump(self, n_spectra, dst=None, spectra=None, inv_scale=None):
         """Last X-engine call of an integration, its result written straight to

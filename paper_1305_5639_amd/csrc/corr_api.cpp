@@ -441,6 +441,49 @@ corr_status corr_fengine_real8(corr_handle h, const int8_t *d_samples, int64_t l
 
 }  // extern "C"
 
+extern "C" {
+
+corr_status corr_fx(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
+                    const float *d_inv_scale, int32_t chunk_spectra) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (!d_volts || !aligned(d_volts, 8)) return fail(h, CORR_E_INVALID_ARG, "d_volts must be 8-byte aligned");
+    if (d_inv_scale && !aligned(d_inv_scale, 4)) return fail(h, CORR_E_INVALID_ARG, "d_inv_scale misaligned");
+    if (n_spectra < 1) return fail(h, CORR_E_INVALID_ARG, "n_spectra must be >= 1");
+    if (chunk_spectra < 1 || chunk_spectra % h->TB || chunk_spectra > h->p.n_integrate)
+        return fail(h, CORR_E_INVALID_ARG,
+                    "chunk_spectra must be a multiple of the time block and at most n_integrate");
+    if (ld_samples < (int64_t)n_spectra * h->C)
+        return fail(h, CORR_E_INVALID_ARG, "ld_samples < n_spectra * n_channels");
+    if (h->prec == P_INT8 && !d_inv_scale) return fail(h, CORR_E_INVALID_ARG, "int8 needs a per-channel scale");
+    if (h->batch_member) return fail(h, CORR_E_STATE, "sub-array handles integrate with corr_xengine_batched");
+    if (h->prec == P_INT8 && h->n_integrated + n_spectra > CORR_INT8_MAX_INTEGRATE)
+        return fail(h, CORR_E_OVERFLOW, "int8 integration would exceed 66572 spectra since the last reset");
+
+    hipError_t e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "scale2 launch");
+    const float2 *v = static_cast<const float2 *>(d_volts);
+    int last = 0;
+    for (int32_t s0 = 0; s0 < n_spectra; s0 += chunk_spectra) {
+        const int ns = std::min(chunk_spectra, n_spectra - s0);
+        e = launch_fengine(h->prec, h->C, h->N, v + (int64_t)s0 * h->C, ld_samples, ns,
+                           d_inv_scale ? d_inv_scale : h->unit_scale, h->twiddle, h->spec, h->lay,
+                           FScratch{h->gscr, h->gscr_bytes}, 0, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "fengine launch");
+        e = launch_xengine(h->prec, effective_tile(h), h->C, h->N, ns, h->spec, h->lay,
+                           h->prec == P_INT8 ? nullptr : h->scale2, h->acc, h->acc, h->acc_zero ? 1 : 0, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "xengine launch");
+        h->acc_zero = false;
+        last = ns;
+    }
+    h->n_held = last;
+    h->held_from_fengine = true;
+    h->n_integrated += n_spectra;
+    h->err.clear();
+    return CORR_OK;
+}
+
+}  // extern "C"
+
 // Checks of an X-engine call, the ingest of caller spectra, and the scale the
 // X-engine applies (shared by corr_xengine and corr_xengine_dump).
 static corr_status prepare_x(corr_ctx *h, const void *d_spectra, int32_t n_spectra, const float *d_inv_scale,
