@@ -93,6 +93,8 @@ def parse():
                     help="skip the 8-bit real-sample section (128 to 3072 streams, transform length 256)")
     ap.add_argument("--no-shapes", action="store_true",
                     help="skip the X-engine timings at the 512- and 1024-input shapes")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the F + X autotuner (block size x spectra order) on the main workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "xengine_traffic.txt"),
@@ -190,6 +192,34 @@ def run_form(torch, corr, synth, w, prec, volts, steps, warmup):
     wall = (time.perf_counter() - t0) / steps
     timing = {"fengine_ms": ftimer.stats(), "xengine_and_dump_ms": xtimer.stats()}
     return c, out, inv, wall, ftimer.mean_ms(), xtimer.mean_ms(), timing
+
+
+def run_autotune(torch, corr, synth, w, volts, precs):
+    """corr_autotune_fx on the main workload for each precision: the chosen
+    X-engine block size and spectra order, the F + X time (X timed on 256
+    channels and scaled) of the built-in choice and of the chosen one, and
+    whether the tuned handle's integration equals the default one's."""
+    A = w.n_integrate
+    out = {}
+    for prec in precs:
+        inv = torch.from_numpy(synth.inv_scale(w, prec)).to("cuda") if prec != "fp32" else None
+        with corr.Correlator(w.n_stations, w.n_pols, w.n_channels, A, prec) as c:
+            c.fengine(volts, A, inv)
+            c.xengine(A)
+            ref = c.dump()
+        with corr.Correlator(w.n_stations, w.n_pols, w.n_channels, A, prec) as c:
+            t0 = time.perf_counter()
+            t = c.autotune_fx(volts, A, inv)
+            torch.cuda.synchronize()
+            t["tuner_s"] = time.perf_counter() - t0
+            c.xengine(A)
+            t["output_equal_default"] = bool(torch.equal(c.dump(), ref))
+        del ref
+        t["gain"] = t["ms_default"] / t["ms_tuned"] if t["ms_tuned"] > 0 else None
+        out[prec] = t
+        log(f"autotune {prec}: tile {t['tile']} order {t['time_block_major']}, F+X {t['ms_default']:.3f} -> "
+            f"{t['ms_tuned']:.3f} ms, equal {t['output_equal_default']}")
+    return out
 
 
 def run_pipelined(torch, corr, w, prec, volts, steps, warmup, ref):
@@ -815,6 +845,10 @@ def main():
                      "step_tcmacs": cmacs / wall_f / 1e12, "timing": timing_f}
         log(f"{fp}: step {wall_f * 1e3:.3f} ms, F {f_ms_f:.3f} ms, X {x_ms_f:.3f} ms")
 
+    tuned = None
+    if not args.no_autotune:
+        tuned = run_autotune(torch, corr, synth, w, volts, [prec] + list(forms))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -885,6 +919,7 @@ def main():
         "roofline": roofline,
         "forms": forms,
         "pipelined": pipelined,
+        "autotune": tuned,
         "equal_accuracy": equal,
         "xengine_shapes": shapes,
         "batched": batched,

@@ -320,12 +320,49 @@ CORR_API corr_status corr_set_tile(corr_handle h, int32_t tile);
  * Autotuner: time the X-engine with each block size on the first n_spectra
  * held spectra (at most 256 channels, into scratch accumulators, so the
  * integration is untouched), keep the fastest for this handle and write it
- * to *tile (may be NULL).  Results are cached per (precision, inputs, time
- * blocks) for the process, and in the text file named by the environment
- * variable CORR_TUNE_CACHE when it is set.  Synchronises the stream;
- * CORR_E_STATE while the stream is being captured into a graph.
+ * to *tile (may be NULL).  Results are cached per (device architecture,
+ * precision, inputs rounded up to 64, channels, time blocks, spectra order)
+ * for the process, and in the text file named by the environment variable
+ * CORR_TUNE_CACHE when it is set.  Synchronises the stream; CORR_E_STATE
+ * while the stream is being captured into a graph.
  */
 CORR_API corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile);
+
+/*
+ * Order of the held spectra in device memory: time-block-major (1), channel-
+ * major (0) or the built-in rule (-1: time-block-major from 512 inputs or
+ * 2048 channels, or when a channel's row of one time block is under 1 KB).
+ * Results do not depend on it; speed does.  Changing it drops the held
+ * spectra (the next X-engine call needs a new F-engine call).  Batch
+ * sub-arrays: CORR_E_STATE.
+ */
+CORR_API corr_status corr_set_spectra_layout(corr_handle h, int32_t time_block_major);
+
+/* A configuration chosen by corr_autotune_fx. */
+typedef struct {
+    int32_t tile;             /* X-engine block size, 64 or 128 */
+    int32_t time_block_major; /* order of the held spectra (corr_set_spectra_layout) */
+    int32_t default_tile;     /* the built-in choices the timings compare against */
+    int32_t default_time_block_major;
+    float ms_default;         /* F + X time of the built-in choice (-1: taken from the cache) */
+    float ms_tuned;           /* F + X time of the chosen configuration (-1: from the cache) */
+} corr_tuning;
+
+/*
+ * F + X autotuner: times the F-engine (every channel) and the X-engine (at
+ * most 256 channels, into scratch accumulators, scaled up to all channels)
+ * on these voltages for both spectra orders and both block sizes, keeps the
+ * fastest for the handle, and channelises the voltages once more in the
+ * chosen order, so the handle then holds their spectra as after
+ * corr_fengine (the accumulators are not touched).  Arguments as for
+ * corr_fengine (n_spectra <= n_integrate).  Results are cached per (device
+ * architecture, precision, inputs rounded up to 64, channels, time blocks)
+ * for the process and in the file named by CORR_TUNE_CACHE when set.
+ * Synchronises the stream; CORR_E_STATE while capturing and for batch
+ * sub-arrays.  *out (may be NULL) receives the choice and both timings.
+ */
+CORR_API corr_status corr_autotune_fx(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
+                                      const float *d_inv_scale, corr_tuning *out);
 
 /*
  * Batched form: many sub-arrays of uneven size (stations, channels,

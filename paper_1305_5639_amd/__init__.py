@@ -13,4 +13,5 @@ from .corr import (  # noqa: F401
     corr_status_string, corr_visibility_bytes, corr_xengine, lib, make_params, corr_set_tile,
     corr_autotune, corr_create_batched, corr_batch_get, corr_xengine_batched, corr_destroy_batched,
     corr_xengine_rect, corr_fengine_real8, corr_xengine_dump, corr_xengine_noalloc, corr_fx,
+    corr_set_spectra_layout, corr_autotune_fx, corr_tuning,
 )

@@ -45,6 +45,7 @@ ABI_FUNCTIONS = (
     "corr_set_tile", "corr_autotune", "corr_create_batched", "corr_batch_get",
     "corr_xengine_batched", "corr_destroy_batched", "corr_xengine_rect", "corr_fengine_real8",
     "corr_fengine_at", "corr_fengine_real8_at", "corr_xengine_dump", "corr_xengine_noalloc", "corr_fx",
+    "corr_set_spectra_layout", "corr_autotune_fx",
 )
 
 
@@ -59,6 +60,17 @@ class corr_params(ctypes.Structure):
         ("order", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("device_mem_cap", ctypes.c_uint64),
+    ]
+
+
+class corr_tuning(ctypes.Structure):
+    _fields_ = [
+        ("tile", ctypes.c_int32),
+        ("time_block_major", ctypes.c_int32),
+        ("default_tile", ctypes.c_int32),
+        ("default_time_block_major", ctypes.c_int32),
+        ("ms_default", ctypes.c_float),
+        ("ms_tuned", ctypes.c_float),
     ]
 
 
@@ -111,12 +123,14 @@ def lib() -> ctypes.CDLL:
         L.corr_xengine_rect.argtypes = [P, i32, i32, i32, i32, i32, P, i32]
         L.corr_xengine_noalloc.argtypes = [PP, P, i32, P, P, i32, P]
         L.corr_fx.argtypes = [P, P, i64, i32, P, i32]
+        L.corr_set_spectra_layout.argtypes = [P, i32]
+        L.corr_autotune_fx.argtypes = [P, P, i64, i32, P, ctypes.POINTER(corr_tuning)]
         for f in ("corr_create", "corr_destroy", "corr_fengine", "corr_fengine_real8", "corr_fengine_at",
                   "corr_fengine_real8_at", "corr_xengine", "corr_xengine_dump",
                   "corr_xengine_rect", "corr_xengine_noalloc", "corr_fx",
                   "corr_dump_visibilities", "corr_copy_spectra", "corr_get_counts", "corr_set_tile",
                   "corr_autotune", "corr_create_batched", "corr_batch_get", "corr_xengine_batched",
-                  "corr_destroy_batched"):
+                  "corr_destroy_batched", "corr_set_spectra_layout", "corr_autotune_fx"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -288,6 +302,20 @@ def corr_autotune(h, n_spectra: int) -> int:
     return t.value
 
 
+def corr_set_spectra_layout(h, time_block_major: int) -> None:
+    _check(lib().corr_set_spectra_layout(h, int(time_block_major)), "corr_set_spectra_layout", h)
+
+
+def corr_autotune_fx(h, volts, n_spectra: int, inv_scale=None, ld_samples: int | None = None) -> dict:
+    x, ld = _rows(volts, ld_samples)
+    t = corr_tuning()
+    _check(lib().corr_autotune_fx(h, x, int(ld), int(n_spectra), _ptr(inv_scale), ctypes.byref(t)),
+           "corr_autotune_fx", h)
+    return {"tile": t.tile, "time_block_major": t.time_block_major,
+            "default": {"tile": t.default_tile, "time_block_major": t.default_time_block_major},
+            "ms_default": t.ms_default, "ms_tuned": t.ms_tuned}
+
+
 def corr_create_batched(params_list, stream=None) -> ctypes.c_void_p:
     arr = (corr_params * len(params_list))(*params_list)
     b = ctypes.c_void_p()
@@ -391,6 +419,14 @@ class Correlator:
 
     def autotune(self, n_spectra):
         return corr_autotune(self.handle, n_spectra)
+
+    def set_spectra_layout(self, time_block_major):
+        corr_set_spectra_layout(self.handle, time_block_major)
+
+    def autotune_fx(self, volts, n_spectra, inv_scale=None, ld_samples=None):
+        """Choose block size and spectra order on these voltages; the handle
+        then holds their spectra (as after fengine)."""
+        return corr_autotune_fx(self.handle, volts, n_spectra, inv_scale, ld_samples)
 
     def close(self):
         if self.handle and self._owned:

@@ -26,6 +26,8 @@ struct corr_ctx {
     corr_params p{};
     int N = 0, C = 0, prec = 0, TB = 0, n_tb_cap = 0;
     SpecLayout lay{};                 // strides of the spectra buffer
+    bool tb_major = false;            // its order (time-block-major or channel-major)
+    std::string arch;                 // the device's architecture name (tuning cache key)
     int64_t B = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -168,9 +170,26 @@ const float *x_scale(const corr_ctx *h) {
     return h->prec == P_FP32 ? nullptr : h->scale2_user;
 }
 
-// Autotune cache: (precision, inputs, time blocks) -> block size.
+// Autotune cache.  Key: the device's architecture name, the precision, the
+// inputs rounded up to 64 (the smaller block size), the channels, the time
+// blocks timed and (for the X-engine-only tuner) the spectra order; value:
+// the block size and, for the F + X tuner, the spectra order.  Kept for the
+// process and, when CORR_TUNE_CACHE names a file, appended to it as lines
+//   fx <arch> <prec> <N/64> <C> <n_tb> <tile> <tb_major>
+//   x  <arch> <prec> <N/64> <C> <n_tb> <tb_major> <tile>
+// (other lines are ignored).
+struct TuneKey {
+    std::string arch;
+    int kind, prec, nb, C, n_tb, order;       // kind 0: X-engine only, 1: F + X
+    bool operator<(const TuneKey &o) const {
+        return std::tie(arch, kind, prec, nb, C, n_tb, order) < std::tie(o.arch, o.kind, o.prec, o.nb, o.C, o.n_tb, o.order);
+    }
+};
+struct TuneVal {
+    int tile, tb_major;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, int> g_tune;
+std::map<TuneKey, TuneVal> g_tune;
 bool g_tune_loaded = false;
 
 void tune_load_locked() {
@@ -180,20 +199,39 @@ void tune_load_locked() {
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    int p, n, t, tile;
-    while (std::fscanf(f, "%d %d %d %d", &p, &n, &t, &tile) == 4)
-        if (tile == 64 || tile == 128) g_tune[{p, n, t}] = tile;
+    char line[512], kind[8], arch[128];
+    while (std::fgets(line, sizeof line, f)) {
+        int p, nb, C, nt, v1, v2;
+        if (std::sscanf(line, "%7s %127s %d %d %d %d %d %d", kind, arch, &p, &nb, &C, &nt, &v1, &v2) != 8) continue;
+        if (!std::strcmp(kind, "fx") && (v1 == 64 || v1 == 128) && (v2 == 0 || v2 == 1))
+            g_tune[{arch, 1, p, nb, C, nt, 0}] = {v1, v2};
+        else if (!std::strcmp(kind, "x") && (v1 == 0 || v1 == 1) && (v2 == 64 || v2 == 128))
+            g_tune[{arch, 0, p, nb, C, nt, v1}] = {v2, v1};
+    }
     std::fclose(f);
 }
 
-void tune_store_locked(int p, int n, int t, int tile) {
-    g_tune[{p, n, t}] = tile;
+void tune_store_locked(const TuneKey &k, TuneVal v) {
+    g_tune[k] = v;
     const char *path = std::getenv("CORR_TUNE_CACHE");
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d\n", p, n, t, tile);
+    if (k.kind == 1)
+        std::fprintf(f, "fx %s %d %d %d %d %d %d\n", k.arch.c_str(), k.prec, k.nb, k.C, k.n_tb, v.tile, v.tb_major);
+    else
+        std::fprintf(f, "x %s %d %d %d %d %d %d\n", k.arch.c_str(), k.prec, k.nb, k.C, k.n_tb, k.order, v.tile);
     std::fclose(f);
+}
+
+// The device's architecture name (gcnArchName, e.g. "gfx950:sramecc+:xnack-").
+std::string device_arch(int dev) {
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    for (char &c : a)
+        if (c == ' ') c = '_';
+    return a.empty() ? "unknown" : a;
 }
 
 }  // namespace
@@ -270,7 +308,8 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
     h->prec = prec;
     h->TB = TB;
     h->n_tb_cap = n_tb_cap;
-    h->lay = spec_layout(C, N, n_tb_cap, elem_bytes(prec));
+    h->tb_major = default_tb_major(C, N, elem_bytes(prec));
+    h->lay = spec_layout_of(C, N, n_tb_cap, h->tb_major);
     h->B = B;
     h->stream = static_cast<hipStream_t>(hip_stream);
     h->spec_bytes = spec_bytes;
@@ -287,6 +326,7 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
         delete h;
         return fail(nullptr, CORR_E_HIP, m);
     }
+    h->arch = device_arch(h->device);
     if (!params->device_mem_cap) {
         size_t fr = 0, tot = 0;
         e = hipMemGetInfo(&fr, &tot);
@@ -698,12 +738,13 @@ corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile_out) {
     if (e != hipSuccess) return hip_fail(h, e, "hipStreamIsCapturing");
     if (cs != hipStreamCaptureStatusNone) return fail(h, CORR_E_STATE, "cannot autotune while capturing");
     const int n_tb = (n_spectra + h->TB - 1) / h->TB;
+    const TuneKey key{h->arch, 0, h->prec, (h->N + 63) / 64, h->C, n_tb, h->tb_major ? 1 : 0};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
-        auto it = g_tune.find({h->prec, h->N, n_tb});
+        auto it = g_tune.find(key);
         if (it != g_tune.end()) {
-            h->tile = it->second;
+            h->tile = it->second.tile;
             if (tile_out) *tile_out = h->tile;
             return CORR_OK;
         }
@@ -743,9 +784,127 @@ corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile_out) {
     h->tile = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_store_locked(h->prec, h->N, n_tb, best);
+        tune_store_locked(key, {best, h->tb_major ? 1 : 0});
     }
     if (tile_out) *tile_out = best;
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_set_spectra_layout(corr_handle h, int32_t time_block_major) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (time_block_major < -1 || time_block_major > 1)
+        return fail(h, CORR_E_INVALID_ARG, "time_block_major must be -1, 0 or 1");
+    if (h->batch_member) return fail(h, CORR_E_STATE, "the batch plan holds its sub-arrays' layouts");
+    const bool tb = time_block_major < 0 ? default_tb_major(h->C, h->N, elem_bytes(h->prec)) : time_block_major == 1;
+    if (tb != h->tb_major) {
+        h->tb_major = tb;
+        h->lay = spec_layout_of(h->C, h->N, h->n_tb_cap, tb);
+        h->n_held = 0;                                   // the held spectra were in the other order
+        h->held_from_fengine = false;
+    }
+    h->err.clear();
+    return CORR_OK;
+}
+
+corr_status corr_autotune_fx(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
+                             const float *d_inv_scale, corr_tuning *out) {
+    if (!h) return fail(nullptr, CORR_E_INVALID_ARG, "handle is NULL");
+    if (!d_volts || !aligned(d_volts, 8)) return fail(h, CORR_E_INVALID_ARG, "d_volts must be 8-byte aligned");
+    if (d_inv_scale && !aligned(d_inv_scale, 4)) return fail(h, CORR_E_INVALID_ARG, "d_inv_scale misaligned");
+    if (n_spectra < 1 || n_spectra > h->p.n_integrate)
+        return fail(h, CORR_E_INVALID_ARG, "need 1 <= n_spectra <= n_integrate");
+    if (ld_samples < (int64_t)n_spectra * h->C)
+        return fail(h, CORR_E_INVALID_ARG, "ld_samples < n_spectra * n_channels");
+    if (h->prec == P_INT8 && !d_inv_scale) return fail(h, CORR_E_INVALID_ARG, "int8 needs a per-channel scale");
+    if (h->batch_member) return fail(h, CORR_E_STATE, "the batch plan holds its sub-arrays' layouts");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(h->stream, &cs);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) return fail(h, CORR_E_STATE, "cannot autotune while capturing");
+
+    const int n_tb = (n_spectra + h->TB - 1) / h->TB;
+    const bool def_tb = default_tb_major(h->C, h->N, elem_bytes(h->prec));
+    const int def_tile = (h->N <= 64 || h->prec == P_FP32) ? 64 : 128;
+    const TuneKey key{h->arch, 1, h->prec, (h->N + 63) / 64, h->C, n_tb, 0};
+    TuneVal best{def_tile, def_tb ? 1 : 0};
+    float best_ms = 0, def_ms = 0;
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            best = it->second;
+            cached = true;
+        }
+    }
+    const float *inv = d_inv_scale ? d_inv_scale : h->unit_scale;
+    const float2 *v = static_cast<const float2 *>(d_volts);
+    if ((e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream)) != hipSuccess) return hip_fail(h, e, "scale2");
+    if (!cached) {
+        // F-engine on every channel, X-engine on at most 256 of them into
+        // scratch accumulators (the integration is untouched), scaled up to C
+        const int Ct = std::min(h->C, 256);
+        void *tmp = nullptr;
+        if ((e = hipMalloc(&tmp, (size_t)Ct * h->B * 8)) != hipSuccess) return hip_fail(h, e, "hipMalloc autotune");
+        hipEvent_t ev[3];
+        for (auto &x : ev) (void)hipEventCreate(&x);
+        best_ms = 0;
+        bool first = true;
+        for (int o = 0; o < 2 && e == hipSuccess; ++o) {
+            const bool tb = o == 0 ? def_tb : !def_tb;
+            const SpecLayout lay = spec_layout_of(h->C, h->N, h->n_tb_cap, tb);
+            for (int tile : {64, 128}) {
+                float ms = 0;
+                for (int r = 0; e == hipSuccess && r < 3; ++r) {
+                    (void)hipEventRecord(ev[0], h->stream);
+                    e = launch_fengine(h->prec, h->C, h->N, v, ld_samples, n_spectra, inv, h->twiddle, h->spec, lay,
+                                       FScratch{h->gscr, h->gscr_bytes}, 0, h->stream);
+                    (void)hipEventRecord(ev[1], h->stream);
+                    if (e == hipSuccess)
+                        e = launch_xengine(h->prec, tile, Ct, h->N, n_spectra, h->spec, lay,
+                                           h->prec == P_INT8 ? nullptr : h->scale2, tmp, tmp, 1, h->stream);
+                    (void)hipEventRecord(ev[2], h->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+                    float tf = 0, tx = 0;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&tf, ev[0], ev[1]);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&tx, ev[1], ev[2]);
+                    const float t = tf + tx * (float)h->C / (float)Ct;
+                    if (r > 0) ms = (r == 1 || t < ms) ? t : ms;           // the first run warms up
+                }
+                if (e != hipSuccess) break;
+                if (tb == def_tb && tile == def_tile) def_ms = ms;
+                if (first || ms < best_ms) {
+                    best = {tile, tb ? 1 : 0};
+                    best_ms = ms;
+                    first = false;
+                }
+            }
+        }
+        for (auto &x : ev) (void)hipEventDestroy(x);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return hip_fail(h, e, "autotune");
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store_locked(key, best);
+    }
+    // keep the choice and leave the handle holding these spectra in its order
+    h->tile = best.tile;
+    h->tb_major = best.tb_major == 1;
+    h->lay = spec_layout_of(h->C, h->N, h->n_tb_cap, h->tb_major);
+    e = launch_fengine(h->prec, h->C, h->N, v, ld_samples, n_spectra, inv, h->twiddle, h->spec, h->lay,
+                       FScratch{h->gscr, h->gscr_bytes}, 0, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "fengine launch");
+    h->n_held = n_spectra;
+    h->held_from_fengine = true;
+    if (out) {
+        out->tile = best.tile;
+        out->time_block_major = best.tb_major;
+        out->default_tile = def_tile;
+        out->default_time_block_major = def_tb ? 1 : 0;
+        out->ms_default = cached ? -1.0f : def_ms;
+        out->ms_tuned = cached ? -1.0f : best_ms;
+    }
     h->err.clear();
     return CORR_OK;
 }

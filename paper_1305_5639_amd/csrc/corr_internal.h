@@ -46,18 +46,26 @@ struct SpecLayout {
 // int8 F-engine 12.2 -> 9.3 ms; 4096 x 1024 x 1024 FP8: 28.7 -> 18.1 ms;
 // 128 channels x 2048 inputs: F 0.61 -> 0.55 ms, X 1.37 -> 1.26 ms), and
 // slower for the 1024 x 256 x 1000 case (FP32 F-engine 1.13 -> 1.47 ms).
-inline SpecLayout spec_layout(int C, int N, int n_tb_cap, int elem) {
+inline bool default_tb_major(int C, int N, int elem) { return N >= 512 || C >= 2048 || C * elem < 1024; }
+inline SpecLayout spec_layout_of(int C, int N, int n_tb_cap, bool tb_major) {
     const int64_t row = (int64_t)N * 2 * kRowBytes;
-    (void)n_tb_cap;
-    const bool tb_major = N >= 512 || C >= 2048 || C * elem < 1024;
     if (tb_major) return {row + kChannelPad, (int64_t)C * (row + kChannelPad)};
     return {(int64_t)n_tb_cap * row + kChannelPad, row};
 }
-// Bytes of the spectra buffer: every row of n_tb_cap time blocks, plus padding.
+inline SpecLayout spec_layout(int C, int N, int n_tb_cap, int elem) {
+    return spec_layout_of(C, N, n_tb_cap, default_tb_major(C, N, elem));
+}
+// Bytes of the spectra buffer: every row of n_tb_cap time blocks, plus
+// padding, in whichever of the two orders needs more (a handle can switch).
 inline int64_t spec_buffer_bytes(int C, int N, int n_tb_cap, int elem) {
-    const SpecLayout l = spec_layout(C, N, n_tb_cap, elem);
-    const int64_t a = (int64_t)(C - 1) * l.ks + (int64_t)(n_tb_cap - 1) * l.ts + (int64_t)N * 2 * kRowBytes;
-    return a + kChannelPad;
+    (void)elem;
+    int64_t most = 0;
+    for (int o = 0; o < 2; ++o) {
+        const SpecLayout l = spec_layout_of(C, N, n_tb_cap, o == 1);
+        const int64_t a = (int64_t)(C - 1) * l.ks + (int64_t)(n_tb_cap - 1) * l.ts + (int64_t)N * 2 * kRowBytes;
+        most = a + kChannelPad > most ? a + kChannelPad : most;
+    }
+    return most;
 }
 
 inline int elem_bytes(int prec) { return prec == P_FP32 ? 4 : (prec == P_FP16 ? 2 : 1); }

@@ -144,6 +144,8 @@ def test_null_arguments():
     assert L.corr_fengine_real8_at(None, None, 0, 1, None, 0) == corr.CORR_E_INVALID_ARG
     assert L.corr_xengine_dump(None, None, 1, None, None) == corr.CORR_E_INVALID_ARG
     assert L.corr_fx(None, None, 0, 1, None, 64) == corr.CORR_E_INVALID_ARG
+    assert L.corr_set_spectra_layout(None, 1) == corr.CORR_E_INVALID_ARG
+    assert L.corr_autotune_fx(None, None, 0, 1, None, None) == corr.CORR_E_INVALID_ARG
     assert L.corr_dump_visibilities(None, None, 0, 0) == corr.CORR_E_INVALID_ARG
     assert L.corr_copy_spectra(None, None, 0) == corr.CORR_E_INVALID_ARG
     a, b = ctypes.c_int32(), ctypes.c_int64()
