@@ -239,8 +239,8 @@ struct OutMap {
 // Time blocks stream through a two-slot LDS ring by direct global-to-LDS
 // copies: the copy of time block t + 1 is issued when block t starts and
 // lands while its MFMAs run.  The copies bypass registers, so the block
-// keeps two workgroups per CU.  Both operand slabs are always copied (a
-// diagonal block copies the same rows twice).  Rows past N copy row N - 1;
+// keeps two workgroups per CU.  A diagonal block copies its one slab of rows
+// once and reads both operands from it.  Rows past N copy row N - 1;
 // they only feed outputs that are not written.  In the last time block,
 // spectra past the valid count are zeroed in LDS once it lands.
 template <int PREC, int TILE, bool RECT = false>
@@ -259,7 +259,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     constexpr int OPB = TILE * RB;                      // one operand slab of a stage
     constexpr int STG = 2 * OPB;                        // one stage
     constexpr int L = STG / (NW * 1024);                // 1 KB copies per wave per stage
-    static_assert(2 * STG == ring_bytes(TILE) && L < 64, "ring geometry");
+    static_assert(2 * STG == ring_bytes(TILE) && L < 64 && L % 2 == 0, "ring geometry");
     const int wave = tid >> 6, lane = tid & 63;
     const int wi = wave / WC, wj = wave % WC;
     const int m = lane & 31, h = lane >> 5;
@@ -283,12 +283,16 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     }
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)smem;
     gu8 *const gbase = (gu8 *)base_k;
+    // A diagonal block's two slabs are the same rows: it copies slab 0 only
+    // (copies j < L / 2 cover stage bytes [0, OPB)) and reads both operands
+    // from it.
     auto issue = [&](int t) {
         gu8 *src = gbase + (int64_t)t * t_stride;
         const uint32_t dst = lds0 + (uint32_t)((t & 1) * STG);
 #pragma unroll
         for (int j = 0; j < L; ++j)
-            dma16(src + rowoff[j], __builtin_amdgcn_readfirstlane(dst + (uint32_t)((NW * j + wave) * 1024)));
+            if (!diag || j < L / 2)
+                dma16(src + rowoff[j], __builtin_amdgcn_readfirstlane(dst + (uint32_t)((NW * j + wave) * 1024)));
     };
     // Zero spectra >= tv of the landed last time block.
     auto fix_tail = [&](int t) {
@@ -327,7 +331,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
         }
 
     const uint8_t *pa0 = smem + (wi * QS + m) * RB;
-    const uint8_t *pb0 = smem + OPB + (wj * 32 + m) * RB;
+    const uint8_t *pb0 = smem + (diag ? 0 : OPB) + (wj * 32 + m) * RB;
     const bool tail = tv < TB;
 
     issue(0);
