@@ -372,7 +372,11 @@ CORR_API corr_status corr_autotune_fx(corr_handle h, const void *d_volts, int64_
  * sub-arrays are drained by persistent X-engine launches -- one per block
  * size in use, so at most two -- from eight per-XCD work queues (channels
  * split evenly, largest items first, idle workgroups take work from the
- * other queues).  All sub-arrays share one precision and stream (and one
+ * other queues).  A sub-array whose blocks alone number at least four per
+ * workgroup the GPU holds at its block size fills the GPU by itself and
+ * runs as its own ordinary X-engine launch within the same call (measured
+ * faster than the persistent launch for such sub-arrays, whose unbroken
+ * load runs at a lower clock).  All sub-arrays share one precision and stream (and one
  * F-engine scratch, since their F-engines run in stream order).  Each
  * sub-array is an ordinary handle owned by the batch (corr_batch_get): use
  * corr_fengine, corr_dump_visibilities and corr_autotune on it as usual;

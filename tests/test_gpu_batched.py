@@ -146,6 +146,43 @@ def test_batched_graph_replay_matches_eager():
         b.close()
 
 
+def test_batched_direct_and_persistent_mix_int8():
+    """A sub-array large enough to fill the GPU on its own (256 inputs x 1024
+    channels: 3072 blocks of 128 inputs) runs as its own launch inside
+    corr_xengine_batched, the small ones in the persistent launch; both
+    integrate across calls (the zero flag of each is consumed once), bit-exact
+    against the integer oracle, eagerly and replayed from a graph."""
+    shapes = [(128, 2, 1024, 64)] + SHAPES[:3]
+    say(f"batched direct + persistent int8 {shapes}")
+    vs, invs = _batch_inputs("int8", shapes, seed=30)
+    n = [A for (_, _, _, A) in shapes]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        vd = [torch.from_numpy(v).to(DEV) for v in vs]
+        idd = [torch.from_numpy(x).to(DEV) for x in invs]
+        b = corr.Batch(shapes, "int8", stream=stream)
+        for i, sub in enumerate(b.subs):
+            sub.fengine(vd[i], n[i], idd[i])
+        b.xengine(n)
+        b.xengine(n)                                         # integrates twice
+        got = [sub.dump(reset=True).cpu().numpy().astype(np.int64) for sub in b.subs]
+        sp = [sub.spectra().cpu().numpy() for sub in b.subs]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            b.xengine(n)
+        for rep in range(2):
+            g.replay()
+            stream.synchronize()
+            once = [sub.dump(reset=True).cpu().numpy().astype(np.int64) for sub in b.subs]
+            for i in range(len(shapes)):
+                assert np.array_equal(2 * once[i], got[i]), (rep, i)
+        b.close()
+    for i, (ns, npol, C, A) in enumerate(shapes):
+        chans = sorted({0, 1, C // 2, C - 1})
+        ref = oracle.xengine_i8(spectra_akp_to_apk(sp[i][:, chans]))
+        assert np.array_equal(got[i][chans], 2 * ref), i
+
+
 def test_batched_real_input_sub_arrays_int8_exact():
     """Sub-arrays fed by the real-input F-engine (8-bit real samples): the
     batched X-engine is exact against the integer oracle on each sub-array's
