@@ -318,8 +318,10 @@ CORR_API corr_status corr_set_tile(corr_handle h, int32_t tile);
 
 /*
  * Autotuner: time the X-engine with each block size on the first n_spectra
- * held spectra (at most 256 channels, into scratch accumulators, so the
- * integration is untouched), keep the fastest for this handle and write it
+ * held spectra (on max(256, enough channels for four 128-input blocks per
+ * workgroup slot of the GPU) channels, at most all, into scratch
+ * accumulators, so the integration is untouched), keep the fastest for
+ * this handle and write it
  * to *tile (may be NULL).  Results are cached per (device architecture,
  * precision, inputs rounded up to 64, channels, time blocks, spectra order)
  * for the process, and in the text file named by the environment variable
@@ -349,8 +351,9 @@ typedef struct {
 } corr_tuning;
 
 /*
- * F + X autotuner: times the F-engine (every channel) and the X-engine (at
- * most 256 channels, into scratch accumulators, scaled up to all channels)
+ * F + X autotuner: times the F-engine (every channel) and the X-engine (on
+ * the channels corr_autotune uses, into scratch accumulators, scaled up to
+ * all channels)
  * on these voltages for both spectra orders and both block sizes, keeps the
  * fastest for the handle, and channelises the voltages once more in the
  * chosen order, so the handle then holds their spectra as after

@@ -28,6 +28,7 @@ struct corr_ctx {
     SpecLayout lay{};                 // strides of the spectra buffer
     bool tb_major = false;            // its order (time-block-major or channel-major)
     std::string arch;                 // the device's architecture name (tuning cache key)
+    int num_cus = 256;                // compute units of the device
     int64_t B = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -224,6 +225,17 @@ void tune_store_locked(const TuneKey &k, TuneVal v) {
     std::fclose(f);
 }
 
+// Channels an autotuner times the X-engine on: at least 256, and enough that
+// both block sizes give four workgroups per slot the GPU holds (two of 128
+// inputs or four of 64 per CU), so a small array is timed at throughput, not
+// at the latency of a launch that leaves the GPU half empty.
+int tune_channels(const corr_ctx *h) {
+    const int64_t nb = (h->N + 127) / 128;
+    const int64_t tiles128 = nb * (nb + 1) / 2;
+    const int64_t need = (4 * 2 * (int64_t)h->num_cus + tiles128 - 1) / tiles128;
+    return (int)std::min<int64_t>(h->C, std::max<int64_t>(256, need));
+}
+
 // The device's architecture name (gcnArchName, e.g. "gfx950:sramecc+:xnack-").
 std::string device_arch(int dev) {
     hipDeviceProp_t prop{};
@@ -327,6 +339,11 @@ corr_status corr_create(const corr_params *params, void *hip_stream, corr_handle
         return fail(nullptr, CORR_E_HIP, m);
     }
     h->arch = device_arch(h->device);
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
+            h->num_cus = cus;
+    }
     if (!params->device_mem_cap) {
         size_t fr = 0, tot = 0;
         e = hipMemGetInfo(&fr, &tot);
@@ -749,7 +766,7 @@ corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile_out) {
             return CORR_OK;
         }
     }
-    const int Ct = std::min(h->C, 256);
+    const int Ct = tune_channels(h);
     void *tmp = nullptr;
     if ((e = hipMalloc(&tmp, (size_t)Ct * h->B * 8)) != hipSuccess) return hip_fail(h, e, "hipMalloc autotune");
     hipEvent_t ev[2];
@@ -843,9 +860,9 @@ corr_status corr_autotune_fx(corr_handle h, const void *d_volts, int64_t ld_samp
     const float2 *v = static_cast<const float2 *>(d_volts);
     if ((e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream)) != hipSuccess) return hip_fail(h, e, "scale2");
     if (!cached) {
-        // F-engine on every channel, X-engine on at most 256 of them into
-        // scratch accumulators (the integration is untouched), scaled up to C
-        const int Ct = std::min(h->C, 256);
+        // F-engine on every channel, X-engine on some of them into scratch
+        // accumulators (the integration is untouched), scaled up to C
+        const int Ct = tune_channels(h);
         void *tmp = nullptr;
         if ((e = hipMalloc(&tmp, (size_t)Ct * h->B * 8)) != hipSuccess) return hip_fail(h, e, "hipMalloc autotune");
         hipEvent_t ev[3];

@@ -356,7 +356,9 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
 
     // Epilogue: element r of a 32x32 block is (row 8(r/4) + 4h + r%4, column m).
     // Rows go in batches of EH; each batch's accumulator reads are issued
-    // before any of its writes.  Elements outside the triangle (rectangle) or
+    // before any of its writes.  The writes are streaming (non-temporal) so
+    // that they displace fewer of the spectra rows other blocks still read
+    // from L2 (FP8, 1024 inputs x 4096 channels: 9.45 -> 9.1-9.3 ms).  Elements outside the triangle (rectangle) or
     // past N read a valid address and are not written.  Offsets within a
     // channel fit 32 bits (N(N+1)/2 and N^2 < 2^31 for N <= 8192).
     using E = typename std::conditional<PREC == P_INT8, int, float>::type;
@@ -412,7 +414,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
                     v.x += old[q].x;
                     v.y += old[q].y;
                 }
-                if ((ok >> q) & 1u) out[idx[q]] = v;
+                if ((ok >> q) & 1u) __builtin_nontemporal_store(v, &out[idx[q]]);
             }
         }
     }
