@@ -175,9 +175,11 @@ template <int TILE> struct WaveGrid {
 // + Ai Bi, Im += Ar Bi + Ai (-Br)).  The column fragment is read once, each
 // row block's fragments just before its MFMAs, and (except for FP8, whose
 // MFMA takes both chunks) one 16-byte chunk at a time, which keeps the live
-// fragment registers few enough for four waves per SIMD.  SKIP0: a diagonal
-// wave whose first row block lies wholly above the diagonal leaves it out.
-template <int PREC, int FR, bool SKIP0, typename Acc>
+// fragment registers few enough for four waves per SIMD.  SKIP = 1: a
+// diagonal wave whose first row block lies wholly above the diagonal leaves
+// it out; SKIP = 2: a wave whose last row block lies wholly past the inputs
+// leaves that out.
+template <int PREC, int FR, int SKIP, typename Acc>
 __device__ __forceinline__ void wave_stage(Acc (&re)[FR], Acc (&im)[FR], const uint8_t *pa, const uint8_t *pb,
                                            const int (&off)[2][kNT]) {
     constexpr int NC = PREC == P_FP8 ? 1 : kNT;        // chunk groups per stage
@@ -190,7 +192,7 @@ __device__ __forceinline__ void wave_stage(Acc (&re)[FR], Acc (&im)[FR], const u
         const typename X::Frag nb = X::neg(b0);
 #pragma unroll
         for (int f = 0; f < FR; ++f) {
-            if (SKIP0 && f == 0) continue;
+            if ((SKIP == 1 && f == 0) || (SKIP == 2 && f == FR - 1)) continue;
             const typename X::Frag a0 = X::load(pa + f * 32 * kRB, off[0] + t * NTC);
             const typename X::Frag a1 = X::load(pa + f * 32 * kRB, off[1] + t * NTC);
 #pragma unroll
@@ -265,9 +267,14 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     const int m = lane & 31, h = lane >> 5;
     const bool diag = !RECT && I0 == J0;
     // on a diagonal block, a wave whose columns all lie right of its rows
-    // idles; one whose first 32 rows do skips that row block
-    const bool active = !(diag && 32 * wj > wi * QS + QS - 1);
+    // idles; one whose first 32 rows do skips that row block.  A wave whose
+    // rows or columns all lie past the inputs (past the rectangle) idles; one
+    // whose last 32 rows do skips that row block.
+    const int rlim = RECT ? om.r_end : N, clim = RECT ? om.c_end : N;
     const bool dwave = FR > 1 && diag && 32 * wj > wi * QS + 31;
+    const bool lwave = FR > 1 && I0 + wi * QS + (FR - 1) * 32 >= rlim;
+    const bool active = !(diag && 32 * wj > wi * QS + QS - 1) && I0 + wi * QS < rlim && J0 + wj * 32 < clim &&
+                        !(dwave && lwave);
     const int S = n_tb;                                 // stages
 
     // Copy j of this wave covers stage bytes [g KB, (g + 1) KB), g = NW j + wave;
@@ -347,9 +354,11 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
             const int so = (t & 1) * STG;
             // one uniform branch per stage keeps the MFMA stream branch-free
             if (dwave)
-                wave_stage<PREC, FR, true>(re, im, pa0 + so, pb0 + so, off);
+                wave_stage<PREC, FR, 1>(re, im, pa0 + so, pb0 + so, off);
+            else if (PREC != P_FP8 && lwave)           // (a third FP8 body would spill)
+                wave_stage<PREC, FR, 2>(re, im, pa0 + so, pb0 + so, off);
             else
-                wave_stage<PREC, FR, false>(re, im, pa0 + so, pb0 + so, off);
+                wave_stage<PREC, FR, 0>(re, im, pa0 + so, pb0 + so, off);
         }
     }
     if (!active) return;
@@ -373,7 +382,7 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     constexpr int EH = FR == 1 ? 16 : 8;
 #pragma unroll
     for (int f = 0; f < FR; ++f) {
-        if (dwave && f == 0) continue;
+        if ((dwave && f == 0) || (lwave && f == FR - 1)) continue;
 #pragma unroll
         for (int hh = 0; hh < 16 / EH; ++hh) {
             int idx[EH];
