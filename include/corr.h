@@ -362,7 +362,8 @@ typedef struct {
  * architecture, precision, inputs rounded up to 64, channels, time blocks)
  * for the process and in the file named by CORR_TUNE_CACHE when set.
  * Synchronises the stream; CORR_E_STATE while capturing and for batch
- * sub-arrays.  *out (may be NULL) receives the choice and both timings.
+ * sub-arrays.  *out (may be NULL) receives the choice and both timings.  The
+ * spectra held before the call are dropped (on an error, none are held).
  */
 CORR_API corr_status corr_autotune_fx(corr_handle h, const void *d_volts, int64_t ld_samples, int32_t n_spectra,
                                       const float *d_inv_scale, corr_tuning *out);

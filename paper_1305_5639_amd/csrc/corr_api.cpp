@@ -236,6 +236,24 @@ int tune_channels(const corr_ctx *h) {
     return (int)std::min<int64_t>(h->C, std::max<int64_t>(256, need));
 }
 
+// Timing events and a scratch buffer owned by an autotuner call.
+struct TuneScope {
+    hipEvent_t ev[3] = {};
+    int n_ev = 0;
+    void *tmp = nullptr;
+    hipError_t create(int n_events, size_t tmp_bytes) {
+        for (n_ev = 0; n_ev < n_events; ++n_ev) {
+            const hipError_t e = hipEventCreate(&ev[n_ev]);
+            if (e != hipSuccess) return e;
+        }
+        return hipMalloc(&tmp, tmp_bytes);
+    }
+    ~TuneScope() {
+        for (int i = 0; i < n_ev; ++i) (void)hipEventDestroy(ev[i]);
+        if (tmp) (void)hipFree(tmp);
+    }
+};
+
 // The device's architecture name (gcnArchName, e.g. "gfx950:sramecc+:xnack-").
 std::string device_arch(int dev) {
     hipDeviceProp_t prop{};
@@ -767,36 +785,34 @@ corr_status corr_autotune(corr_handle h, int32_t n_spectra, int32_t *tile_out) {
         }
     }
     const int Ct = tune_channels(h);
-    void *tmp = nullptr;
-    if ((e = hipMalloc(&tmp, (size_t)Ct * h->B * 8)) != hipSuccess) return hip_fail(h, e, "hipMalloc autotune");
-    hipEvent_t ev[2];
-    (void)hipEventCreate(&ev[0]);
-    (void)hipEventCreate(&ev[1]);
     const int cand[2] = {64, 128};
     float best_ms = 0;
     int best = 0;
-    for (int c : cand) {
-        float ms = 0;
-        e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->spec, h->lay, x_scale(h), tmp, tmp, 1, h->stream);
-        for (int r = 0; e == hipSuccess && r < 3; ++r) {
-            (void)hipEventRecord(ev[0], h->stream);
-            e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->spec, h->lay, x_scale(h), tmp, tmp, 1,
-                               h->stream);
-            (void)hipEventRecord(ev[1], h->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
-            float t = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
-            ms = (r == 0 || t < ms) ? t : ms;
-        }
-        if (e != hipSuccess) break;
-        if (!best || ms < best_ms) {
-            best = c;
-            best_ms = ms;
+    {
+        TuneScope sc;
+        if ((e = sc.create(2, (size_t)Ct * h->B * 8)) != hipSuccess) return hip_fail(h, e, "autotune setup");
+        void *tmp = sc.tmp;
+        for (int c : cand) {
+            float ms = 0;
+            e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->spec, h->lay, x_scale(h), tmp, tmp, 1, h->stream);
+            for (int r = 0; e == hipSuccess && r < 3; ++r) {
+                e = hipEventRecord(sc.ev[0], h->stream);
+                if (e == hipSuccess)
+                    e = launch_xengine(h->prec, c, Ct, h->N, n_spectra, h->spec, h->lay, x_scale(h), tmp, tmp, 1,
+                                       h->stream);
+                if (e == hipSuccess) e = hipEventRecord(sc.ev[1], h->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(sc.ev[1]);
+                float t = 0;
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, sc.ev[0], sc.ev[1]);
+                ms = (r == 0 || t < ms) ? t : ms;
+            }
+            if (e != hipSuccess) break;
+            if (!best || ms < best_ms) {
+                best = c;
+                best_ms = ms;
+            }
         }
     }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(h, e, "autotune");
     h->tile = best;
     {
@@ -858,15 +874,17 @@ corr_status corr_autotune_fx(corr_handle h, const void *d_volts, int64_t ld_samp
     }
     const float *inv = d_inv_scale ? d_inv_scale : h->unit_scale;
     const float2 *v = static_cast<const float2 *>(d_volts);
+    h->n_held = 0;                                        // the spectra buffer is overwritten from here on
+    h->held_from_fengine = false;
     if ((e = launch_scale2(h->C, d_inv_scale, h->scale2, h->stream)) != hipSuccess) return hip_fail(h, e, "scale2");
     if (!cached) {
         // F-engine on every channel, X-engine on some of them into scratch
         // accumulators (the integration is untouched), scaled up to C
         const int Ct = tune_channels(h);
-        void *tmp = nullptr;
-        if ((e = hipMalloc(&tmp, (size_t)Ct * h->B * 8)) != hipSuccess) return hip_fail(h, e, "hipMalloc autotune");
-        hipEvent_t ev[3];
-        for (auto &x : ev) (void)hipEventCreate(&x);
+        TuneScope sc;
+        if ((e = sc.create(3, (size_t)Ct * h->B * 8)) != hipSuccess) return hip_fail(h, e, "autotune setup");
+        void *tmp = sc.tmp;
+        hipEvent_t *ev = sc.ev;
         best_ms = 0;
         bool first = true;
         for (int o = 0; o < 2 && e == hipSuccess; ++o) {
@@ -875,14 +893,15 @@ corr_status corr_autotune_fx(corr_handle h, const void *d_volts, int64_t ld_samp
             for (int tile : {64, 128}) {
                 float ms = 0;
                 for (int r = 0; e == hipSuccess && r < 3; ++r) {
-                    (void)hipEventRecord(ev[0], h->stream);
-                    e = launch_fengine(h->prec, h->C, h->N, v, ld_samples, n_spectra, inv, h->twiddle, h->spec, lay,
-                                       FScratch{h->gscr, h->gscr_bytes}, 0, h->stream);
-                    (void)hipEventRecord(ev[1], h->stream);
+                    e = hipEventRecord(ev[0], h->stream);
+                    if (e == hipSuccess)
+                        e = launch_fengine(h->prec, h->C, h->N, v, ld_samples, n_spectra, inv, h->twiddle, h->spec,
+                                           lay, FScratch{h->gscr, h->gscr_bytes}, 0, h->stream);
+                    if (e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
                     if (e == hipSuccess)
                         e = launch_xengine(h->prec, tile, Ct, h->N, n_spectra, h->spec, lay,
                                            h->prec == P_INT8 ? nullptr : h->scale2, tmp, tmp, 1, h->stream);
-                    (void)hipEventRecord(ev[2], h->stream);
+                    if (e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
                     if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
                     float tf = 0, tx = 0;
                     if (e == hipSuccess) e = hipEventElapsedTime(&tf, ev[0], ev[1]);
@@ -899,8 +918,6 @@ corr_status corr_autotune_fx(corr_handle h, const void *d_volts, int64_t ld_samp
                 }
             }
         }
-        for (auto &x : ev) (void)hipEventDestroy(x);
-        (void)hipFree(tmp);
         if (e != hipSuccess) return hip_fail(h, e, "autotune");
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_store_locked(key, best);
