@@ -112,3 +112,36 @@ def test_autotune_fx_rejects():
                 c.autotune_fx(v, bad, inv)
         with pytest.raises(corr.CorrError):
             c.autotune_fx(v, 64, None)                            # int8 needs a scale
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_forced_order_caller_spectra_rect_and_append_int8(order):
+    """Every path that touches the held spectra under a forced order: caller
+    spectra in and out, the triangle and the rectangle, and an integration
+    appended in two F-engine pieces, bit-exact against the integer oracle."""
+    N, C, A = 40, 256, 130
+    say(f"forced order {order}: int8 N={N} C={C} A={A}")
+    S = synth.int8_spectra(A, C, N, seed=order + 17)                  # [A][C][N][2]
+    with corr.Correlator(N, 1, C, A, "int8") as c:
+        c.set_spectra_layout(order)
+        c.xengine(A, torch.from_numpy(S).to(DEV))
+        got = c.dump().cpu().numpy().astype(np.int64)
+        assert np.array_equal(c.spectra().cpu().numpy(), S)
+        rect = c.xengine_rect(24, 16, 0, 24, A).cpu().numpy().astype(np.int64)     # rows 24..39 x columns 0..23
+    Sc = spectra_akp_to_apk(S).astype(np.int64)                        # [A][N][C][2]
+    assert np.array_equal(got, oracle.xengine_i8(spectra_akp_to_apk(S)))
+    x = Sc[..., 0] + 1j * Sc[..., 1]                                   # [A][N][C]
+    ref_rect = np.einsum("aik,ajk->kij", np.conj(x[:, 24:40]), x[:, 0:24])
+    assert np.array_equal(rect[..., 0], ref_rect.real.astype(np.int64))
+    assert np.array_equal(rect[..., 1], ref_rect.imag.astype(np.int64))
+    w = synth.small(f"order-append-{order}", 20, 2, C, A, seed=order + 5)
+    v = torch.from_numpy(synth.voltages(w)).to(DEV)
+    inv = torch.from_numpy(synth.inv_scale(w, "int8")).to(DEV)
+    with corr.Correlator(20, 2, C, 128, "int8") as c:
+        c.set_spectra_layout(order)
+        c.fengine(v, 64, inv)                                          # spectra 0..63
+        c.fengine(v[:, 64 * C:], 64, inv, ld_samples=v.shape[1], first_spectrum=64)   # 64..127
+        c.xengine(128)
+        got = c.dump().cpu().numpy().astype(np.int64)
+        sp = c.spectra().cpu().numpy()
+    assert np.array_equal(got, oracle.xengine_i8(spectra_akp_to_apk(sp)))
