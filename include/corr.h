@@ -321,7 +321,8 @@ CORR_API corr_status corr_set_tile(corr_handle h, int32_t tile);
  * held spectra (on max(256, enough channels for four 128-input blocks per
  * workgroup slot of the GPU) channels, at most all, into scratch
  * accumulators, so the integration is untouched), keep the fastest for
- * this handle and write it
+ * this handle (the built-in choice unless another is at least 2% faster)
+ * and write it
  * to *tile (may be NULL).  Results are cached per (device architecture,
  * precision, inputs rounded up to 64, channels, time blocks, spectra order)
  * for the process, and in the text file named by the environment variable
@@ -355,7 +356,8 @@ typedef struct {
  * the channels corr_autotune uses, into scratch accumulators, scaled up to
  * all channels)
  * on these voltages for both spectra orders and both block sizes, keeps the
- * fastest for the handle, and channelises the voltages once more in the
+ * fastest for the handle (the built-in choice unless another is at least 2%
+ * faster), and channelises the voltages once more in the
  * chosen order, so the handle then holds their spectra as after
  * corr_fengine (the accumulators are not touched).  Arguments as for
  * corr_fengine (n_spectra <= n_integrate).  Results are cached per (device
