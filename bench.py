@@ -129,6 +129,20 @@ def read_traffic(path, key):
     return float(v) if v else None
 
 
+def x_roofline(prec, N, C, A, ms):
+    """The X-engine launch against its roofline: algorithmic bytes (spectra
+    read, N(N+1)/2 x C x 8-byte visibilities written on a first call), their
+    rate, and the fraction of the ceiling min(MFMA peak, AI x HBM peak)
+    reached, as the time at that ceiling over the measured time."""
+    cm = N * (N + 1) // 2 * C * A
+    nbytes = N * C * A * 2 * ELEM_BYTES[prec] + N * (N + 1) // 2 * C * 8
+    t_mfma = 8 * cm / (PEAK[prec] * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    return {"algorithmic_bytes": nbytes, "algorithmic_gbs": nbytes / (ms * 1e-3) / 1e9,
+            "bound": "mfma" if t_mfma >= t_hbm else "hbm",
+            "ceiling_ms": 1e3 * max(t_mfma, t_hbm), "ceiling_frac": max(t_mfma, t_hbm) / (ms * 1e-3)}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -365,7 +379,8 @@ def run_shapes(torch, corr, reps=3):
                                  "xengine_tcmacs": tc, "mfma_frac": 8 * tc / PEAK[prec],
                                  "spectra_bytes": nbytes, "caller_spectra_xengine_ms": caller_ms,
                                  "ingest_ms": ingest_ms, "ingest_tbs": 2 * nbytes / (ingest_ms * 1e-3) / 1e12,
-                                 "export_ms": export_ms, "export_tbs": 2 * nbytes / (export_ms * 1e-3) / 1e12}
+                                 "export_ms": export_ms, "export_tbs": 2 * nbytes / (export_ms * 1e-3) / 1e12,
+                                 "x_roofline": x_roofline(prec, N, C, A, ms)}
         log(f"shape {name} {prec}: X {ms:.3f} ms, {tc:.1f} TCMAC/s, {100 * 8 * tc / PEAK[prec]:.1f}% of MFMA peak; "
             f"{nbytes / 1e9:.2f} GB caller spectra in {ingest_ms:.2f} ms, out {export_ms:.2f} ms")
         c.close()
@@ -842,7 +857,8 @@ def main():
                      "fengine_hbm_gbs": (N * A * C * (8 + 2 * ELEM_BYTES[fp])) / (f_ms_f * 1e-3) / 1e9,
                      "xengine_tcmacs": xt, "xengine_mfma_frac": 8 * xt / PEAK[fp],
                      "xengine_speedup_vs_fp32": x_ms / x_ms_f if prec == "fp32" else None,
-                     "step_tcmacs": cmacs / wall_f / 1e12, "timing": timing_f}
+                     "step_tcmacs": cmacs / wall_f / 1e12, "timing": timing_f,
+                     "x_roofline": x_roofline(fp, N, C, A, x_ms_f)}
         log(f"{fp}: step {wall_f * 1e3:.3f} ms, F {f_ms_f:.3f} ms, X {x_ms_f:.3f} ms")
 
     tuned = None
@@ -917,6 +933,7 @@ def main():
         "fengine_hbm_gbs": (N * A * C * (8 + 2 * ELEM_BYTES[prec])) / (f_ms * 1e-3) / 1e9,
         "timing": timing,
         "roofline": roofline,
+        "x_roofline": x_roofline(prec, N, C, A, x_ms),
         "forms": forms,
         "pipelined": pipelined,
         "autotune": tuned,
