@@ -157,7 +157,7 @@ bool default_dump(const corr_params *p) { return p->layout == CORR_TRI_LOWER && 
 bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
 // Default block size when none was set or tuned, from measured X-engine
-// speed on MI355X at 256..1024 inputs: 64-input blocks (five workgroups per
+// speed on MI355X at 256..1024 inputs: 64-input blocks (four workgroups per
 // CU) win for FP32, 128-input blocks (eight 64x32 waves, more operand reuse)
 // for the FP16, int8 and FP8 forms.
 int effective_tile(const corr_ctx *h) {
