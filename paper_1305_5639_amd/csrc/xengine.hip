@@ -345,7 +345,12 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     for (int t = 0; t < S; ++t) {
         wait_vm<0>();                                   // this wave's copies of block t landed
         __syncthreads();                                // block t landed; the other slot is free
+        // The copies go out at a raised wave priority, ahead of the MFMAs of
+        // the other waves on the SIMD (FP32, 1024 x 4096 x 1024: 137.0 ->
+        // 133.3 ms; the FP16, FP8 and int8 forms unchanged within 1%).
+        __builtin_amdgcn_s_setprio(2);
         if (t + 1 < S) issue(t + 1);
+        __builtin_amdgcn_s_setprio(0);
         if (tail && t == S - 1) {
             fix_tail(t);
             __syncthreads();
