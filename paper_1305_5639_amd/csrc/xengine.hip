@@ -341,13 +341,16 @@ __device__ __forceinline__ void tile(uint8_t *smem, const uint8_t *__restrict__ 
     const uint8_t *pb0 = smem + (diag ? 0 : OPB) + (wj * 32 + m) * RB;
     const bool tail = tv < TB;
 
+    __builtin_amdgcn_s_setprio(2);                     // (see the copies in the loop)
     issue(0);
+    __builtin_amdgcn_s_setprio(0);
     for (int t = 0; t < S; ++t) {
         wait_vm<0>();                                   // this wave's copies of block t landed
         __syncthreads();                                // block t landed; the other slot is free
         // The copies go out at a raised wave priority, ahead of the MFMAs of
         // the other waves on the SIMD (FP32, 1024 x 4096 x 1024: 137.0 ->
-        // 133.3 ms; the FP16, FP8 and int8 forms unchanged within 1%).
+        // 133.3 ms; the FP16, FP8 and int8 forms unchanged within 1%; the
+        // first block's copies too: a further 0.2-1%).
         __builtin_amdgcn_s_setprio(2);
         if (t + 1 < S) issue(t + 1);
         __builtin_amdgcn_s_setprio(0);
